@@ -1,0 +1,80 @@
+"""Oracle: direct FP64 correlation, power plane and gradients (numpy).
+
+Test infrastructure only.  The correlation technique (Sec. 2, eq. 23)
+recovers the response at bin r by correlating the M bins around r with the
+complex-conjugated template.  The paper prints the sum with garbled limits;
+the reading used here (taps j in [0, M) at bin offsets e_j = j - M/2, the
+spectrum taken as zero outside [0, N)) is
+
+    Y[z][r] = sum_j A[r + e_j] * conj(T[z][j]),   P[z][r] = |Y[z][r]|^2,
+
+for every r in [0, N).  The overlap-save FFT evaluation (Sec. 3, Fig. 1) is
+a fast way of computing exactly this sum; the oracle evaluates the sum
+itself, with no FFT, no blocking and no reordering.
+
+Gradients of the loss  Lw = sum_{z,r} w[z][r] P[z][r]  (not in the paper;
+written from the definition above, in PyTorch's complex convention
+grad = dLw/dRe + i dLw/dIm):
+    g[z][r]      = 2 w[z][r] Y[z][r]
+    grad_A[k]    = sum_z sum_j T[z][j] g[z][k - e_j]      (g = 0 outside [0, N))
+    grad_T[z][j] = sum_r conj(g[z][r]) A[r + e_j]
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _padded(A: np.ndarray, M: int) -> np.ndarray:
+    """A placed at offset M/2 of a zero array of length N + M, so that
+    A[r + e_j] = pad[r + j] for every r in [0, N) and j in [0, M)."""
+    N = len(A)
+    pad = np.zeros(N + M, dtype=np.complex128)
+    pad[M // 2:M // 2 + N] = A
+    return pad
+
+
+def correlate(A, T) -> np.ndarray:
+    """Complex correlation Y[K][N] (complex128)."""
+    A = np.asarray(A, dtype=np.complex128)
+    T = np.asarray(T, dtype=np.complex128)
+    K, M = T.shape
+    N = len(A)
+    pad = _padded(A, M)
+    Y = np.zeros((K, N), dtype=np.complex128)
+    for j in range(M):
+        Y += np.conj(T[:, j])[:, None] * pad[j:j + N][None, :]
+    return Y
+
+
+def power(A, T) -> np.ndarray:
+    """f-fdot power plane P[K][N] = |Y|^2 (float64)."""
+    Y = correlate(A, T)
+    return Y.real ** 2 + Y.imag ** 2
+
+
+def loss(A, T, w) -> float:
+    """Lw = sum w * P."""
+    return float(np.sum(np.asarray(w, dtype=np.float64) * power(A, T)))
+
+
+def grads(A, T, w):
+    """(grad_A [N], grad_T [K][M]) of Lw, complex128, PyTorch convention."""
+    A = np.asarray(A, dtype=np.complex128)
+    T = np.asarray(T, dtype=np.complex128)
+    w = np.asarray(w, dtype=np.float64)
+    K, M = T.shape
+    N = len(A)
+    g = 2.0 * w * correlate(A, T)
+    # gpad[:, M + r] = g[:, r]; then g[:, k - e_j] = gpad[:, k + M + M/2 - j]
+    gpad = np.zeros((K, N + 2 * M), dtype=np.complex128)
+    gpad[:, M:M + N] = g
+    gA = np.zeros(N, dtype=np.complex128)
+    for j in range(M):
+        start = M + M // 2 - j
+        gA += (T[:, j][:, None] * gpad[:, start:start + N]).sum(axis=0)
+    pad = _padded(A, M)
+    gT = np.zeros((K, M), dtype=np.complex128)
+    gc = np.conj(g)
+    for j in range(M):
+        gT[:, j] = gc @ pad[j:j + N]
+    return gA, gT
