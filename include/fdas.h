@@ -1,0 +1,150 @@
+/*
+ * fdas.h -- C ABI of the MI355X (gfx950) FDAS correlation library.
+ *
+ * Fourier Domain Acceleration Search, correlation step (Dimoudi et al.
+ * 2018, "Pulsar acceleration searches on the GPU for the Square Kilometre
+ * Array"): the complex Fourier amplitudes of a spectrum are correlated with
+ * a bank of K complex FIR templates, one per trial frequency derivative z,
+ * by overlap-save FFT segments, and the |.|^2 f-fdot power plane is
+ * written out (Sec. 3, Fig. 1 and Fig. 3 caption; Sec. 4.1 workflow).
+ *
+ * Definition of the result (Sec. 2, eq. 23): with taps j in [0, M) at bin
+ * offsets e_j = j - M/2 and the spectrum A taken as zero outside [0, N),
+ *     Y[z][r] = sum_j A[r + e_j] * conj(T[z][j]),   P[z][r] = |Y[z][r]|^2,
+ * for r in [0, N).  The segment length L (Sec. 3: blocks of L = B + M
+ * bins, B useful outputs each) is a performance parameter: every supported
+ * L gives the same plane up to FP32 rounding.
+ *
+ * Conventions for every call:
+ *  - Complex data is fdas_cf32 (interleaved float re, im; the layout of a
+ *    torch.complex64 element).  Pointers suffixed _dev are device pointers
+ *    on the current HIP device; _host are host pointers.
+ *  - The caller owns every buffer.  Calls on the hot path (fdas_correlate,
+ *    fdas_correlate_batched, fdas_correlate_backward) never allocate.
+ *  - Calls are asynchronous on `stream` (0 = the null stream) and validate
+ *    all arguments before launching anything; on any non-zero status no
+ *    kernel has been launched and no output was touched.
+ *  - Outputs are fully overwritten, never accumulated into.
+ *  - Status codes: FDAS_OK 0; FDAS_INVALID_ARG 1 (null/misaligned pointer,
+ *    negative size, inconsistent grid); FDAS_UNSUPPORTED 2 (geometry outside
+ *    the supported set: L not a power of two in [256, 8192], M odd, M < 2 or
+ *    M > L/2, K < 1 or K > 4096); FDAS_WORKSPACE_TOO_SMALL 3; FDAS_HIP_ERROR 4
+ *    (a HIP call failed; fdas_last_error() has the text).  Nothing aborts
+ *    and no C++ exception crosses the ABI.
+ */
+#ifndef FDAS_H
+#define FDAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    float re, im;
+} fdas_cf32;
+
+enum {
+    FDAS_OK = 0,
+    FDAS_INVALID_ARG = 1,
+    FDAS_UNSUPPORTED = 2,
+    FDAS_WORKSPACE_TOO_SMALL = 3,
+    FDAS_HIP_ERROR = 4
+};
+
+/* Library version string (static storage). */
+const char *fdas_version(void);
+
+/* Static text for a status code. */
+const char *fdas_status_string(int status);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char *fdas_last_error(void);
+
+/*
+ * Number of trial templates for the z grid z_k = (k - (K-1)/2) * dz,
+ * k in [0, K), i.e. -zmax .. +zmax in steps of dz, K = 2*zmax/dz + 1.
+ * zmax >= 0, dz > 0 and zmax must be an integer multiple of dz (relative
+ * tolerance 1e-9), else FDAS_INVALID_ARG.  The paper's grid steps z by 2
+ * ("one template", Sec. 5.2).
+ */
+int fdas_num_templates(double zmax, double dz, int *K);
+
+/*
+ * Predicted normalised Fourier response R(q, z) of a unit-amplitude
+ * constant-fdot signal (Sec. 2, text before eq. 23), evaluated on the host
+ * in FP64: the response at bin k of a signal that sits at bin r at
+ * mid-observation and drifts by z bins over the observation, q = r - k,
+ *     R(q, z) = int_0^1 exp(i 2 pi [q u + z (u^2 - u)/2]) du.
+ * Writes the real and imaginary parts.  Never fails for finite input.
+ */
+int fdas_template_response(double q, double z, double *re, double *im);
+
+/*
+ * Template bank on the host: taps_host[k*M + j] = R(j - M/2, z_k), FP64
+ * rounded once to FP32.  Templates are not renormalised after truncation
+ * to M taps.  M even, 2 <= M <= 16384.  Writes K*M elements.
+ */
+int fdas_make_templates_host(double zmax, double dz, int M, fdas_cf32 *taps_host);
+
+/* Number of fdas_cf32 elements of a prepared bank: (K + 1) * L. */
+int64_t fdas_bank_elems(int K, int L);
+
+/*
+ * Prepare the Fourier-domain bank for segment length L from K templates of
+ * M taps (Sec. 3, Fig. 1: each filter is placed at the two ends of an
+ * L-array so that it is centred on bin 0 -- tap j at index (M/2 - j) mod L,
+ * zeros strictly between M/2 and L - M/2 + 1 -- conjugated, and Fourier
+ * transformed).  Layout of bank_dev ((K + 1) * L elements, 16-byte
+ * aligned):
+ *   rows 0..K-1 : H_z[k] = (1/L) sum_j conj(T[z][j]) exp(-2 pi i ((M/2-j) mod L) k / L),
+ *                 natural frequency order, accumulated in FP64, rounded once;
+ *   row K       : twiddles exp(-2 pi i n / L), n in [0, L), FP64 rounded once.
+ * The 1/L of the inverse DFT (printed without it in Sec. 4.2) is folded in.
+ * taps_dev: K*M elements, 8-byte aligned.  Not on the hot path.
+ */
+int fdas_prepare_bank(const fdas_cf32 *taps_dev, int K, int M, int L,
+                      fdas_cf32 *bank_dev, hipStream_t stream);
+
+/*
+ * Templates for the grid (zmax, dz) with M taps, computed on the host in
+ * FP64 and copied to taps_dev (K*M elements, required); if bank_dev is not
+ * NULL the bank for segment length L is prepared from those taps as by
+ * fdas_prepare_bank (L is ignored when bank_dev is NULL).  Blocks the host
+ * until the copy has been consumed.  Not on the hot path.
+ */
+int fdas_make_templates(double zmax, double dz, int M, int L,
+                        fdas_cf32 *taps_dev, fdas_cf32 *bank_dev,
+                        hipStream_t stream);
+
+/*
+ * Forward correlation of one spectrum: the fused overlap-save pipeline of
+ * Sec. 3 / Sec. 4.2 (segment load with zero fill, forward FFT, K template
+ * multiplies, inverse FFTs, |.|^2 and edge rejection) in one launch.
+ *   spec_dev  : N complex bins, 8-byte aligned (read only);
+ *   N         : bins, 0 <= N < 2^40 (N = 0 is a no-op);
+ *   bank_dev  : prepared bank for (K, M, L) from fdas_prepare_bank;
+ *   plane_dev : K*N floats, row-major [z][r], 4-byte aligned; every element
+ *               is written.
+ * Segment s covers outputs [s*B, s*B + B), B = L - M, and reads input bins
+ * [s*B - M/2, s*B - M/2 + L).
+ */
+int fdas_correlate(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf32 *bank_dev,
+                   int K, int M, int L, float *plane_dev, hipStream_t stream);
+
+/*
+ * Same as fdas_correlate with an explicit launch shape, for tuning:
+ * zchunk templates per workgroup (1..K; 0 = library default).
+ */
+int fdas_correlate_ex(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf32 *bank_dev,
+                      int K, int M, int L, float *plane_dev, int zchunk,
+                      hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDAS_H */

@@ -1,0 +1,173 @@
+"""ctypes binding of libfdas.so: the C-ABI calls under the same names.
+
+Argument marshalling only -- every step of the correlation runs in the HIP
+kernels of the library.  Tensors are torch device tensors (complex64 /
+float32); the stream defaults to torch's current stream on the tensor's
+device.  If the library is missing the import of this module fails loudly:
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdas.so")
+
+FDAS_OK = 0
+FDAS_INVALID_ARG = 1
+FDAS_UNSUPPORTED = 2
+FDAS_WORKSPACE_TOO_SMALL = 3
+FDAS_HIP_ERROR = 4
+
+# (name, restype, argtypes) of every symbol declared in include/fdas.h
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+_SZ = ctypes.c_size_t
+SIGNATURES = [
+    ("fdas_version", ctypes.c_char_p, []),
+    ("fdas_status_string", ctypes.c_char_p, [_I]),
+    ("fdas_last_error", ctypes.c_char_p, []),
+    ("fdas_num_templates", _I, [_D, _D, ctypes.POINTER(_I)]),
+    ("fdas_template_response", _I, [_D, _D, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    ("fdas_make_templates_host", _I, [_D, _D, _I, _P]),
+    ("fdas_bank_elems", _I64, [_I, _I]),
+    ("fdas_prepare_bank", _I, [_P, _I, _I, _I, _P, _P]),
+    ("fdas_make_templates", _I, [_D, _D, _I, _I, _P, _P, _P]),
+    ("fdas_correlate", _I, [_P, _I64, _P, _I, _I, _I, _P, _P]),
+    ("fdas_correlate_ex", _I, [_P, _I64, _P, _I, _I, _I, _P, _I, _P]),
+]
+
+
+class FdasError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        super().__init__(f"{where}: status {status} ({status_string(status)}): {detail}")
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1804_05335_amd.build` (no fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().fdas_status_string(status).decode()
+
+
+def _check(status: int, where: str) -> None:
+    if status != FDAS_OK:
+        raise FdasError(status, where, lib().fdas_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream, t):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _require(t, dtype, name, numel=None):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {numel}")
+
+
+# ---- host-only calls ---------------------------------------------------------
+
+def fdas_version() -> str:
+    return lib().fdas_version().decode()
+
+
+def fdas_num_templates(zmax: float, dz: float) -> int:
+    K = ctypes.c_int(0)
+    _check(lib().fdas_num_templates(zmax, dz, ctypes.byref(K)), "fdas_num_templates")
+    return K.value
+
+
+def fdas_template_response(q: float, z: float) -> complex:
+    re, im = ctypes.c_double(), ctypes.c_double()
+    _check(lib().fdas_template_response(q, z, ctypes.byref(re), ctypes.byref(im)),
+           "fdas_template_response")
+    return complex(re.value, im.value)
+
+
+def fdas_make_templates_host(zmax: float, dz: float, M: int):
+    """Template bank T[K][M] as a numpy complex64 array (host FP64, rounded once)."""
+    import numpy as np
+    K = fdas_num_templates(zmax, dz)
+    out = np.empty((K, M), dtype=np.complex64)
+    _check(lib().fdas_make_templates_host(zmax, dz, M, out.ctypes.data_as(ctypes.c_void_p)),
+           "fdas_make_templates_host")
+    return out
+
+
+def fdas_bank_elems(K: int, L: int) -> int:
+    return int(lib().fdas_bank_elems(K, L))
+
+
+# ---- device calls --------------------------------------------------------------
+
+def fdas_prepare_bank(taps, K: int, M: int, L: int, bank, stream=None) -> None:
+    import torch
+    _require(taps, torch.complex64, "taps", K * M)
+    _require(bank, torch.complex64, "bank", fdas_bank_elems(K, L))
+    _check(lib().fdas_prepare_bank(_ptr(taps), K, M, L, _ptr(bank), _stream(stream, taps)),
+           "fdas_prepare_bank")
+
+
+def fdas_make_templates(zmax: float, dz: float, M: int, L: int, taps, bank=None,
+                        stream=None) -> None:
+    import torch
+    K = fdas_num_templates(zmax, dz)
+    _require(taps, torch.complex64, "taps", K * M)
+    if bank is not None:
+        _require(bank, torch.complex64, "bank", fdas_bank_elems(K, L))
+    _check(lib().fdas_make_templates(zmax, dz, M, L, _ptr(taps), _ptr(bank),
+                                     _stream(stream, taps)), "fdas_make_templates")
+
+
+def fdas_correlate(spec, N: int, bank, K: int, M: int, L: int, plane, stream=None) -> None:
+    import torch
+    _require(spec, torch.complex64, "spec", N)
+    _require(bank, torch.complex64, "bank", fdas_bank_elems(K, L))
+    _require(plane, torch.float32, "plane", K * N)
+    _check(lib().fdas_correlate(_ptr(spec), N, _ptr(bank), K, M, L, _ptr(plane),
+                                _stream(stream, spec)), "fdas_correlate")
+
+
+def fdas_correlate_ex(spec, N: int, bank, K: int, M: int, L: int, plane, zchunk: int,
+                      stream=None) -> None:
+    import torch
+    _require(spec, torch.complex64, "spec", N)
+    _require(bank, torch.complex64, "bank", fdas_bank_elems(K, L))
+    _require(plane, torch.float32, "plane", K * N)
+    _check(lib().fdas_correlate_ex(_ptr(spec), N, _ptr(bank), K, M, L, _ptr(plane), zchunk,
+                                   _stream(stream, spec)), "fdas_correlate_ex")

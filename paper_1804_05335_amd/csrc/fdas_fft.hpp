@@ -1,0 +1,287 @@
+// Workgroup FFTs for gfx950: register codelets plus LDS exchanges.
+//
+// A length-L transform runs on T = L/E lanes of one workgroup, each lane
+// holding E complex values.  Between passes lane t always owns positions
+// t + T*m (m in [0, E)), so every pass reads coalesced rows from LDS.  Pass
+// p (radix R, NS = product of the earlier radices) is a Stockham autosort
+// step: butterfly j gathers positions j + i*L/R, applies the twiddles
+// W_{NS R}^{(j mod NS) i}, runs a radix-R DFT and scatters to
+// (j/NS)*NS*R + (j mod NS) + i*NS.  Input and output are in natural order,
+// and after the last pass each output already sits in the register that the
+// first pass of the next transform reads -- so the forward transform, the
+// template multiply and the inverse transform hand data over in registers
+// with no reordering pass.  This is the property the paper obtains by
+// pairing a decimation-in-frequency forward FFT with a decimation-in-time
+// inverse (Sec. 4.2, around eqs. FFTDIT/FFTDIF); here it comes from the
+// autosort formulation, so the template bank can stay in natural order.
+//
+// Twiddles come from a table exp(-2 pi i n/L) built in FP64 and rounded
+// once (no fast-math trigonometry); each lane loads the few it needs once
+// and keeps them in registers for every transform it runs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fdas {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// a * b
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b)
+{
+    return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -a.x * b.y));
+}
+
+// multiply by the fourth root of unity of the transform direction:
+// -i for the forward transform, +i for the inverse.
+template <bool INV>
+__device__ __forceinline__ float2 rot4(float2 a)
+{
+    return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+template <bool INV>
+__device__ __forceinline__ float2 twiddle(float2 a, float2 w)
+{
+    return INV ? cmulc(a, w) : cmul(a, w);
+}
+
+constexpr float kSqrtHalf = 0.70710678118654752440f;
+constexpr float kCos8 = 0.92387953251128675613f;   // cos(pi/8)
+constexpr float kSin8 = 0.38268343236508977173f;   // sin(pi/8)
+
+// a * W8^1 (forward W8 = exp(-i pi/4); inverse uses the conjugate)
+template <bool INV>
+__device__ __forceinline__ float2 rot8_1(float2 a)
+{
+    return INV ? make_float2((a.x - a.y) * kSqrtHalf, (a.x + a.y) * kSqrtHalf)
+               : make_float2((a.x + a.y) * kSqrtHalf, (a.y - a.x) * kSqrtHalf);
+}
+
+// a * W8^3
+template <bool INV>
+__device__ __forceinline__ float2 rot8_3(float2 a)
+{
+    return INV ? make_float2(-(a.x + a.y) * kSqrtHalf, (a.x - a.y) * kSqrtHalf)
+               : make_float2((a.y - a.x) * kSqrtHalf, -(a.x + a.y) * kSqrtHalf);
+}
+
+// ---- radix-R DFT codelets, natural order in and out ----------------------
+
+template <bool INV>
+__device__ __forceinline__ void dft2(float2 (&x)[2])
+{
+    float2 a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2& x3)
+{
+    float2 t0 = cadd(x0, x2), t1 = csub(x0, x2);
+    float2 t2 = cadd(x1, x3), t3 = rot4<INV>(csub(x1, x3));
+    x0 = cadd(t0, t2);
+    x2 = csub(t0, t2);
+    x1 = cadd(t1, t3);
+    x3 = csub(t1, t3);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2 (&x)[4])
+{
+    dft4<INV>(x[0], x[1], x[2], x[3]);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft8(float2 (&x)[8])
+{
+    float2 e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
+    float2 o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
+    dft4<INV>(e0, e1, e2, e3);
+    dft4<INV>(o0, o1, o2, o3);
+    o1 = rot8_1<INV>(o1);
+    o2 = rot4<INV>(o2);
+    o3 = rot8_3<INV>(o3);
+    x[0] = cadd(e0, o0); x[4] = csub(e0, o0);
+    x[1] = cadd(e1, o1); x[5] = csub(e1, o1);
+    x[2] = cadd(e2, o2); x[6] = csub(e2, o2);
+    x[3] = cadd(e3, o3); x[7] = csub(e3, o3);
+}
+
+// 16 = 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2.
+template <bool INV>
+__device__ __forceinline__ void dft16(float2 (&x)[16])
+{
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2)
+        dft4<INV>(x[n2], x[4 + n2], x[8 + n2], x[12 + n2]);
+    // now x[4 k1 + n2] holds Y[n2][k1]; twiddle by W16^(n2 k1)
+    const float2 w1 = make_float2(kCos8, INV ? kSin8 : -kSin8);
+    const float2 w3 = make_float2(kSin8, INV ? kCos8 : -kCos8);
+    const float2 w9 = make_float2(-kCos8, INV ? -kSin8 : kSin8);
+    x[4 + 1] = twiddle<false>(x[4 + 1], w1);      // n2=1,k1=1: W^1
+    x[4 + 2] = rot8_1<INV>(x[4 + 2]);             // n2=2,k1=1: W^2
+    x[4 + 3] = twiddle<false>(x[4 + 3], w3);      // n2=3,k1=1: W^3
+    x[8 + 1] = rot8_1<INV>(x[8 + 1]);             // n2=1,k1=2: W^2
+    x[8 + 2] = rot4<INV>(x[8 + 2]);               // n2=2,k1=2: W^4
+    x[8 + 3] = rot8_3<INV>(x[8 + 3]);             // n2=3,k1=2: W^6
+    x[12 + 1] = twiddle<false>(x[12 + 1], w3);    // n2=1,k1=3: W^3
+    x[12 + 2] = rot8_3<INV>(x[12 + 2]);           // n2=2,k1=3: W^6
+    x[12 + 3] = twiddle<false>(x[12 + 3], w9);    // n2=3,k1=3: W^9
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+        dft4<INV>(x[4 * k1 + 0], x[4 * k1 + 1], x[4 * k1 + 2], x[4 * k1 + 3]);
+    // x[4 k1 + k2] holds X[k1 + 4 k2]; transpose the 4x4 index back
+    float2 y[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2)
+            y[k1 + 4 * k2] = x[4 * k1 + k2];
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        x[i] = y[i];
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2 (&x)[R])
+{
+    if constexpr (R == 2) dft2<INV>(x);
+    else if constexpr (R == 4) dft4<INV>(x);
+    else if constexpr (R == 8) dft8<INV>(x);
+    else if constexpr (R == 16) dft16<INV>(x);
+    else static_assert(R == 2 || R == 4 || R == 8 || R == 16, "unsupported radix");
+}
+
+// ---- transform plans ---------------------------------------------------------
+
+template <int... Rs>
+struct Radices {};
+
+// Number of register twiddles a lane keeps for the passes from NS on.
+template <int L, int E, int NS, class RL>
+struct TwiddleCount;
+template <int L, int E, int NS>
+struct TwiddleCount<L, E, NS, Radices<>> {
+    static constexpr int value = 0;
+};
+template <int L, int E, int NS, int R, int... Rest>
+struct TwiddleCount<L, E, NS, Radices<R, Rest...>> {
+    static constexpr int value = (NS > 1 ? (E / R) * (R - 1) : 0) +
+                                 TwiddleCount<L, E, NS * R, Radices<Rest...>>::value;
+};
+
+// LDS index with one complex of padding every 16 (breaks power-of-two strides).
+__device__ __forceinline__ int lds_pad(int idx) { return idx + (idx >> 4); }
+
+template <int L>
+struct LdsSize {
+    static constexpr int value = L + L / 16;
+};
+
+// Load the twiddles for passes NS.. into tw[OFF..].
+template <int L, int E, int NS, int OFF, int NTW, int R, int... Rest>
+__device__ __forceinline__ void load_twiddles(float2 (&tw)[NTW], const float2* __restrict__ table, int t)
+{
+    constexpr int T = L / E, NB = E / R;
+    if constexpr (NS > 1) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int j = t + u * T;
+            const int base = (j & (NS - 1)) * (L / (NS * R));
+#pragma unroll
+            for (int i = 1; i < R; ++i)
+                tw[OFF + u * (R - 1) + (i - 1)] = table[base * i];
+        }
+    }
+    if constexpr (sizeof...(Rest) > 0)
+        load_twiddles<L, E, NS * R, OFF + (NS > 1 ? NB * (R - 1) : 0), NTW, Rest...>(tw, table, t);
+}
+
+// Run the passes from NS on.  v holds positions t + T*m; on return v holds
+// the transform at the same positions.  Exchanges ping-pong between the two
+// LDS buffers (one barrier per exchange).
+template <int L, int E, bool INV, int NS, int OFF, int NTW, int R, int... Rest>
+__device__ __forceinline__ void run_passes(float2 (&v)[E], float2*& lds_a, float2*& lds_b,
+                                           const float2 (&tw)[NTW], int t)
+{
+    constexpr int T = L / E, NB = E / R;
+    constexpr bool LAST = sizeof...(Rest) == 0;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        float2 x[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+            x[i] = v[u + i * NB];
+        if constexpr (NS > 1) {
+#pragma unroll
+            for (int i = 1; i < R; ++i)
+                x[i] = twiddle<INV>(x[i], tw[OFF + u * (R - 1) + (i - 1)]);
+        }
+        dft<R, INV>(x);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+                v[u + i * NB] = x[i];
+        } else {
+            const int j = t + u * T;
+            const int idxD = (j / NS) * (NS * R) + (j & (NS - 1));
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+                lds_a[lds_pad(idxD + i * NS)] = x[i];
+        }
+    }
+    if constexpr (!LAST) {
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            v[m] = lds_a[lds_pad(t + m * T)];
+        float2* tmp = lds_a;
+        lds_a = lds_b;
+        lds_b = tmp;
+        run_passes<L, E, INV, NS * R, OFF + (NS > 1 ? NB * (R - 1) : 0), NTW, Rest...>(v, lds_a, lds_b, tw, t);
+    }
+}
+
+template <int L, int E, class RL>
+struct FFT;
+
+template <int L, int E, int... Rs>
+struct FFT<L, E, Radices<Rs...>> {
+    static constexpr int T = L / E;
+    static constexpr int NTW = TwiddleCount<L, E, 1, Radices<Rs...>>::value > 0
+                                   ? TwiddleCount<L, E, 1, Radices<Rs...>>::value : 1;
+    static_assert((1 * ... * Rs) == L, "radices must multiply to L");
+    static_assert(((E % Rs == 0) && ...), "every radix must divide E");
+
+    __device__ static void twiddles(float2 (&tw)[NTW], const float2* __restrict__ table, int t)
+    {
+        load_twiddles<L, E, 1, 0, NTW, Rs...>(tw, table, t);
+    }
+    template <bool INV>
+    __device__ static void run(float2 (&v)[E], float2*& lds_a, float2*& lds_b,
+                               const float2 (&tw)[NTW], int t)
+    {
+        run_passes<L, E, INV, 1, 0, NTW, Rs...>(v, lds_a, lds_b, tw, t);
+    }
+};
+
+// Geometry per segment length: E values per lane and the radix sequence.
+template <int L>
+struct Geometry;
+template <> struct Geometry<256>  { static constexpr int E = 4;  using R = Radices<4, 4, 4, 4>; };
+template <> struct Geometry<512>  { static constexpr int E = 8;  using R = Radices<8, 8, 8>; };
+template <> struct Geometry<1024> { static constexpr int E = 16; using R = Radices<16, 16, 4>; };
+template <> struct Geometry<2048> { static constexpr int E = 16; using R = Radices<16, 16, 8>; };
+template <> struct Geometry<4096> { static constexpr int E = 16; using R = Radices<16, 16, 16>; };
+template <> struct Geometry<8192> { static constexpr int E = 16; using R = Radices<16, 16, 16, 2>; };
+
+}  // namespace fdas

@@ -1,0 +1,24 @@
+// Internal interface between the C-ABI layer and the HIP kernels.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <hip/hip_runtime.h>
+
+namespace fdas {
+
+// Host FP64 response R(q, z) (templates source file).
+std::complex<double> response(double q, double z);
+
+// Bank rows H_z and the twiddle row for segment length L.
+hipError_t launch_prepare_bank(const float2* taps, int K, int M, int L, float2* bank,
+                               hipStream_t s);
+
+// Fused forward correlation of one spectrum; zchunk templates per workgroup.
+hipError_t launch_forward(const float2* spec, int64_t N, const float2* bank, int K, int M,
+                          int L, float* plane, int zchunk, hipStream_t s);
+
+// Default templates-per-workgroup for a problem (occupancy heuristic).
+int default_zchunk(int64_t nseg, int K);
+
+}  // namespace fdas

@@ -1,0 +1,130 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+declared in include/fdas.h, rejects bad arguments with a status before any
+HIP call, and its host FP64 template math agrees with the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1804_05335_amd import _lib
+from oracle import templates as ot
+from tests.quadrature import response_quadrature
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for hdr in os.listdir(os.path.join(ROOT, "include")):
+        if hdr.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", hdr)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(fdas_[a-z0-9_]+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    declared = _declared_symbols()
+    assert "fdas_correlate" in declared and "fdas_prepare_bank" in declared
+    for name in declared:
+        assert hasattr(L, name), name
+    bound = {n for n, _, _ in _lib.SIGNATURES}
+    assert declared == bound
+
+
+def test_status_strings_and_version():
+    assert _lib.fdas_version().startswith("fdas-gfx950")
+    for st in range(5):
+        assert _lib.status_string(st)
+    assert _lib.status_string(99) == "unknown status"
+
+
+def test_num_templates():
+    assert _lib.fdas_num_templates(84.0, 2.0) == 85
+    assert _lib.fdas_num_templates(20.0, 2.0) == 21
+    assert _lib.fdas_num_templates(0.0, 2.0) == 1
+    assert _lib.fdas_num_templates(200.0, 2.0) == 201
+    for zmax, dz in [(3.0, 2.0), (-2.0, 2.0), (4.0, 0.0), (float("nan"), 1.0)]:
+        with pytest.raises(_lib.FdasError) as e:
+            _lib.fdas_num_templates(zmax, dz)
+        assert e.value.status == _lib.FDAS_INVALID_ARG
+    with pytest.raises(_lib.FdasError) as e:
+        _lib.fdas_num_templates(5000.0, 1.0)
+    assert e.value.status == _lib.FDAS_UNSUPPORTED
+
+
+@pytest.mark.parametrize("z", [0.0, 2.0, -2.0, 8.0, -84.0, 200.0, 33.3])
+def test_product_response_matches_oracle(z):
+    q = np.concatenate([np.arange(-300, 301, 7.0), [0.5, -0.25, 12.75, 0.0]])
+    got = np.array([_lib.fdas_template_response(float(x), z) for x in q])
+    ref = ot.response(q, z)
+    assert np.max(np.abs(got - ref)) < 1e-11
+
+
+@pytest.mark.parametrize("z", [1e-4, -3e-3, 0.05])
+def test_product_response_small_z_vs_quadrature(z):
+    # For |z| << 1 the oracle's route multiplies by exp(-i pi q'^2/z) with a
+    # phase of ~1e9 rad and loses digits; the library's route has no large
+    # phase.  Check it against direct quadrature instead.
+    q = np.array([-300.0, -17.0, -1.0, 0.0, 0.5, 1.0, 40.0, 255.0])
+    got = np.array([_lib.fdas_template_response(float(x), z) for x in q])
+    assert np.max(np.abs(got - response_quadrature(q, z))) < 1e-12
+
+
+@pytest.mark.parametrize("zmax,M", [(20.0, 64), (84.0, 256), (84.0, 128), (200.0, 512)])
+def test_product_templates_match_oracle(zmax, M):
+    T = _lib.fdas_make_templates_host(zmax, 2.0, M)
+    ref = ot.templates(zmax, 2.0, M)
+    assert T.shape == ref.shape and T.dtype == np.complex64
+    # FP64 values rounded once to FP32
+    assert np.max(np.abs(T - ref)) <= 6e-8 * np.max(np.abs(ref))
+    assert np.array_equal(T, ref.astype(np.complex64)) or \
+        np.max(np.abs(T - ref.astype(np.complex64))) < 1e-7
+
+
+def _fake(addr):
+    return ctypes.c_void_p(addr)
+
+
+def test_validation_happens_before_any_device_call():
+    L = _lib.lib()
+    sp, bk, pl = _fake(0x1000), _fake(0x2000), _fake(0x3000)
+    cases = [
+        # (N, K, M, L, expected)
+        (1000, 85, 256, 3000, _lib.FDAS_UNSUPPORTED),      # L not a power of two
+        (1000, 85, 256, 128, _lib.FDAS_UNSUPPORTED),       # L too small
+        (1000, 85, 256, 16384, _lib.FDAS_UNSUPPORTED),     # L too large
+        (1000, 85, 255, 2048, _lib.FDAS_UNSUPPORTED),      # M odd
+        (1000, 85, 2048, 2048, _lib.FDAS_UNSUPPORTED),     # M > L/2
+        (1000, 85, 0, 2048, _lib.FDAS_UNSUPPORTED),        # M < 2
+        (1000, 0, 256, 2048, _lib.FDAS_UNSUPPORTED),       # K < 1
+        (-1, 85, 256, 2048, _lib.FDAS_INVALID_ARG),        # N < 0
+        ((1 << 32) + 1, 85, 256, 2048, _lib.FDAS_INVALID_ARG),
+    ]
+    for N, K, M, Ls, want in cases:
+        assert L.fdas_correlate(sp, N, bk, K, M, Ls, pl, None) == want, (N, K, M, Ls)
+        assert L.fdas_last_error()
+    # null and misaligned pointers
+    assert L.fdas_correlate(None, 1000, bk, 85, 256, 2048, pl, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_correlate(_fake(0x1004), 1000, bk, 85, 256, 2048, pl, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_correlate(sp, 1000, _fake(0x2008), 85, 256, 2048, pl, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_correlate(sp, 1000, bk, 85, 256, 2048, _fake(0x3002), None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_correlate_ex(sp, 1000, bk, 85, 256, 2048, pl, 86, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_correlate_ex(sp, 1000, bk, 85, 256, 2048, pl, -1, None) == _lib.FDAS_INVALID_ARG
+    # N = 0 is a no-op that touches nothing, even with NULL buffers
+    assert L.fdas_correlate(None, 0, None, 85, 256, 2048, None, None) == _lib.FDAS_OK
+    # bank preparation
+    assert L.fdas_prepare_bank(None, 85, 256, 2048, bk, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_prepare_bank(sp, 85, 256, 1000, bk, None) == _lib.FDAS_UNSUPPORTED
+    assert L.fdas_prepare_bank(sp, 85, 256, 2048, _fake(0x2008), None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_make_templates(3.0, 2.0, 64, 512, sp, bk, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_make_templates(20.0, 2.0, 64, 512, None, bk, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_make_templates(20.0, 2.0, 63, 512, sp, bk, None) == _lib.FDAS_UNSUPPORTED
+
+
+def test_bank_elems():
+    assert _lib.fdas_bank_elems(85, 2048) == 86 * 2048
+    assert _lib.fdas_bank_elems(0, 2048) == 0

@@ -1,0 +1,207 @@
+"""GPU parity of the fused forward correlation against the FP64 oracle.
+
+Bar (spec tolerance): max |P_gpu - P_oracle| / max P_oracle <= 1e-5,
+with the oracle using its own closed-form templates and the GPU the
+library's.  Full planes at the small workload (2^16 bins, 21 x 64 taps) for
+every segment length, ragged and degenerate sizes with arbitrary taps, and
+sampled outputs at the 2^21-bin / 85-template workload in the launch
+configuration the benchmark times.
+"""
+import numpy as np
+import pytest
+
+import fdas_synth as syn
+from oracle import native
+from oracle import templates as ot
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+LS = [256, 512, 1024, 2048, 4096, 8192]
+
+
+@pytest.fixture(scope="module")
+def fd():
+    import paper_1804_05335_amd as f
+    f.lib()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return f
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def _rel(got, ref):
+    return float(np.max(np.abs(got.astype(np.float64) - ref)) / max(np.max(ref), 1e-30))
+
+
+def _plane(fd, spec_np, bank, K, M, L, zchunk=0):
+    spec = _dev(spec_np.astype(np.complex64))
+    plane = fd.correlate(spec, bank, K, M, L, zchunk=zchunk)
+    torch.cuda.synchronize()
+    return plane.cpu().numpy()
+
+
+@pytest.mark.parametrize("L", LS)
+def test_identity_template_reproduces_input_power(fd, L):
+    # a single tap of 1 at offset 0 (the z = 0 template) makes P = |A|^2:
+    # the forward and inverse segment FFTs must cancel for every L
+    for M in (2, 64, L // 2):
+        taps = np.zeros((1, M), dtype=np.complex64)
+        taps[0, M // 2] = 1.0
+        bank = fd.prepare_bank(_dev(taps), L)
+        B = L - M
+        A = syn.random_spectrum(L + M, 3 * B + 17)
+        P = _plane(fd, A, bank, 1, M, L)[0]
+        ref = np.abs(A.astype(np.complex128)) ** 2
+        assert _rel(P, ref) < TOL, (L, M)
+
+
+@pytest.mark.parametrize("L", LS)
+def test_device_bank_matches_numpy_fft(fd, L):
+    M = min(256, L // 2)
+    taps = syn.random_taps(L, 3, M)
+    bank = fd.prepare_bank(_dev(taps), L).cpu().numpy().reshape(4, L)
+    h = np.zeros((3, L), dtype=np.complex128)
+    for j in range(M):
+        h[:, (M // 2 - j) % L] = np.conj(taps[:, j].astype(np.complex128))
+    H = np.fft.fft(h, axis=1) / L
+    assert np.max(np.abs(bank[:3] - H)) < 2e-7 * np.max(np.abs(H))
+    tw = np.exp(-2j * np.pi * np.arange(L) / L)
+    assert np.max(np.abs(bank[3] - tw)) < 1e-7
+
+
+def test_device_templates_equal_host_templates(fd):
+    taps, _ = fd.make_bank(84.0, 2.0, 256, 2048)
+    host = fd.fdas_make_templates_host(84.0, 2.0, 256)
+    assert np.array_equal(taps.cpu().numpy(), host)
+
+
+@pytest.mark.parametrize("L", [256, 512, 2048, 8192])
+@pytest.mark.parametrize("case", ["one", "short", "B-1", "B", "B+1", "ragged", "M=2", "M=L/2"])
+def test_ragged_and_degenerate_sizes_random_taps(fd, L, case):
+    M = {"M=2": 2, "M=L/2": L // 2}.get(case, min(64, L // 4))
+    B = L - M
+    N = {"one": 1, "short": 7, "B-1": B - 1, "B": B, "B+1": B + 1}.get(case, 4 * B + 13)
+    K = 5
+    taps = syn.random_taps(N + K, K, M)
+    bank = fd.prepare_bank(_dev(taps), L)
+    A = syn.random_spectrum(N + 1, N)
+    P = _plane(fd, A, bank, K, M, L)
+    ref = native.power(A, taps)
+    assert P.shape == (K, N)
+    assert _rel(P, ref) < TOL
+
+
+def test_empty_spectrum_is_a_noop(fd):
+    taps = syn.random_taps(0, 2, 16)
+    bank = fd.prepare_bank(_dev(taps), 256)
+    spec = torch.zeros(0, dtype=torch.complex64, device="cuda:0")
+    plane = torch.full((2, 0), 7.0, device="cuda:0")
+    fd.fdas_correlate(spec, 0, bank, 2, 16, 256, plane)
+    torch.cuda.synchronize()
+
+
+@pytest.fixture(scope="module")
+def w1():
+    return syn.workload(1)
+
+
+@pytest.fixture(scope="module")
+def w1_oracle(w1):
+    return native.power(w1.spectra[0], ot.templates(w1.zmax, w1.dz, w1.M))
+
+
+@pytest.mark.parametrize("L", LS)
+def test_workload1_full_plane(fd, w1, w1_oracle, L):
+    _, bank = fd.make_bank(w1.zmax, w1.dz, w1.M, L)
+    P = _plane(fd, w1.spectra[0], bank, w1.K, w1.M, L)
+    assert _rel(P, w1_oracle) < TOL
+    # the injected signal (r0 = 20000.3, z0 = +8) peaks at its own cell
+    zz, rr = np.unravel_index(np.argmax(P), P.shape)
+    assert ot.z_grid(w1.zmax, w1.dz)[zz] == 8.0 and rr == 20000
+
+
+def test_zchunk_invariance_and_determinism(fd, w1):
+    _, bank = fd.make_bank(w1.zmax, w1.dz, w1.M, w1.L)
+    ref = _plane(fd, w1.spectra[0], bank, w1.K, w1.M, w1.L, zchunk=w1.K)
+    for zc in (0, 1, 4, 7, w1.K):
+        for _ in range(2):
+            assert np.array_equal(_plane(fd, w1.spectra[0], bank, w1.K, w1.M, w1.L, zc), ref)
+
+
+def test_nonfinite_input_is_contained(fd, w1):
+    # A NaN in one bin contaminates the windows that read it; every other
+    # segment's outputs must be bitwise those of the clean run.
+    _, bank = fd.make_bank(w1.zmax, w1.dz, w1.M, w1.L)
+    clean = _plane(fd, w1.spectra[0], bank, w1.K, w1.M, w1.L)
+    A = w1.spectra[0].copy()
+    A[30000] = np.nan
+    P = _plane(fd, A, bank, w1.K, w1.M, w1.L)
+    B = w1.L - w1.M
+    bad = np.zeros(len(A), dtype=bool)
+    for s in range(-(-len(A) // B)):
+        lo = s * B - w1.M // 2
+        if lo <= 30000 < lo + w1.L:
+            bad[s * B:(s + 1) * B] = True
+    assert np.array_equal(P[:, ~bad], clean[:, ~bad])
+
+
+def _sample_points(N, K, M, L, signals, rng):
+    B = L - M
+    cols = []
+    nseg = -(-N // B)
+    for s in range(nseg):                              # every segment boundary
+        c = s * B + np.arange(-2, 3)
+        cols.append(c)
+    for s in rng.choice(nseg, size=6, replace=False):  # full boundary halos
+        cols.append(s * B + np.arange(-M // 2, M // 2))
+    cols.append(np.arange(0, M))                       # first and last columns
+    cols.append(np.arange(N - M, N))
+    for _, _, r, _ in signals:                         # around the signals
+        cols.append(int(round(r)) + np.arange(-48, 49))
+    cols = np.unique(np.clip(np.concatenate(cols), 0, N - 1))
+    zi = np.repeat(np.arange(K), len(cols))
+    ri = np.tile(cols, K)
+    zr = rng.integers(0, K, 400000)                    # random points
+    rr = rng.integers(0, N, 400000)
+    return np.concatenate([zi, zr]).astype(np.int32), np.concatenate([ri, rr]).astype(np.int64)
+
+
+@pytest.fixture(scope="module")
+def w2():
+    return syn.workload(2)
+
+
+@pytest.mark.parametrize("L", [2048, 4096])
+def test_workload2_sampled(fd, w2, L):
+    # 2^21 bins, 85 templates x 256 taps, in the launch configuration the
+    # benchmark times (default zchunk)
+    K, M, N = w2.K, w2.M, len(w2.spectra[0])
+    _, bank = fd.make_bank(w2.zmax, w2.dz, M, L)
+    spec = _dev(w2.spectra[0])
+    plane = fd.correlate(spec, bank, K, M, L)
+    rng = np.random.default_rng(L)
+    zi, ri = _sample_points(N, K, M, L, w2.signals[0], rng)
+    got = plane[torch.from_numpy(zi.astype(np.int64)).cuda(),
+                torch.from_numpy(ri).cuda()].cpu().numpy()
+    ref = native.power_points(w2.spectra[0], ot.templates(w2.zmax, w2.dz, M), zi, ri)
+    assert _rel(got, ref) < TOL
+    # each injected signal peaks where the oracle's plane peaks, and within
+    # one template step of the nearest grid z and a bin of r (Sec. 5.2)
+    zs = ot.z_grid(w2.zmax, w2.dz)
+    T = ot.templates(w2.zmax, w2.dz, M)
+    for _, _, r, z in w2.signals[0]:
+        lo, hi = int(r) - 8, int(r) + 9
+        sub = plane[:, lo:hi].cpu().numpy()
+        ref_sub = native.power(w2.spectra[0], T, lo, hi)
+        assert _rel(sub, ref_sub) < TOL
+        zz, rr = np.unravel_index(np.argmax(sub), sub.shape)
+        # argmax is unique up to near-ties: the oracle's value at the GPU's
+        # peak must be the oracle's maximum to within the tolerance
+        assert ref_sub[zz, rr] >= ref_sub.max() * (1.0 - 2 * TOL)
+        assert abs(zs[zz] - z) <= 1.5 * w2.dz and abs(lo + rr - r) <= 1.0
+    # properties at full size: non-negative and finite everywhere
+    assert bool(torch.isfinite(plane).all()) and float(plane.min()) >= 0.0

@@ -10,22 +10,9 @@ import numpy as np
 import pytest
 
 from oracle import templates as ot
+from tests.quadrature import response_quadrature as _quadrature
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-
-
-def _quadrature(q, z, panels=1200, order=16):
-    """Composite Gauss-Legendre estimate of
-    int_0^1 exp(i 2 pi [q u + z (u^2 - u)/2]) du for every q (vectorised)."""
-    x, wts = np.polynomial.legendre.leggauss(order)
-    edges = np.linspace(0.0, 1.0, panels + 1)
-    a, b = edges[:-1], edges[1:]
-    u = (0.5 * (b - a))[:, None] * x[None, :] + (0.5 * (a + b))[:, None]
-    w = (0.5 * (b - a))[:, None] * wts[None, :]
-    u, w = u.ravel(), w.ravel()
-    q = np.asarray(q, dtype=np.float64)
-    phase = 2 * np.pi * (q[:, None] * u[None, :] + 0.5 * z * (u * u - u)[None, :])
-    return (np.exp(1j * phase) * w[None, :]).sum(axis=1)
 
 
 @pytest.mark.parametrize("z", [0.0, 2.0, -2.0, 8.0, -20.0, 84.0, -84.0, 200.0, -200.0, 7.3])
