@@ -95,14 +95,14 @@ def cpu_baseline(spec_np, zmax, dz, M, K, target_s: float):
     from oracle import native
     from oracle import templates as ot
     T = ot.templates(zmax, dz, M)
-    cols = 256
-    t = time.perf_counter()
-    native.power(spec_np, T, 100000, 100000 + cols)
-    dt = time.perf_counter() - t
-    cols = int(max(256, min(len(spec_np) - 200000, cols * target_s / max(dt, 1e-6))))
-    t = time.perf_counter()
-    native.power(spec_np, T, 100000, 100000 + cols)
-    dt = time.perf_counter() - t
+    cols, dt = 1024, 0.0
+    while True:     # grow the sample until one run takes at least a quarter of the target
+        t = time.perf_counter()
+        native.power(spec_np, T, 100000, 100000 + cols)
+        dt = time.perf_counter() - t
+        if dt >= 0.25 * target_s or cols >= len(spec_np) - 200000:
+            break
+        cols = int(min(len(spec_np) - 200000, cols * max(2.0, 0.5 * target_s / max(dt, 1e-3))))
     return {"value": K * cols / dt, "unit": "points/s", "cores": native.num_threads(),
             "kind": "oracle", "seconds": round(dt, 3),
             "sample": f"all {K} templates x {cols} bins [100000, {100000 + cols}) of the "
@@ -113,11 +113,13 @@ def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--L", default="2048,4096", help="segment lengths to time")
     ap.add_argument("--zchunk", type=int, default=0, help="templates per workgroup (0 = default)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="first run one plain device copy of BYTES (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
@@ -135,6 +137,15 @@ def main() -> int:
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy calibration: {src.numel() * 4} bytes read and written",
+              file=sys.stderr, flush=True)
+        del src, dst
     w = syn.workload(2)
     spec_np = w.spectra[0]
     N, K, M = len(spec_np), w.K, w.M
@@ -160,7 +171,7 @@ def main() -> int:
     alu = {"bound": "alu", "achieved": round(flops / sec / 1e12, 3), "peak": round(ALU_PEAK_TFLOPS, 2),
            "unit": "TFLOP/s"}
     alu["frac"] = round(alu["achieved"] / alu["peak"], 4)
-    traffic = read_traffic(f"forward_L{L}_2e21x85_traffic.txt")
+    traffic = read_traffic(f"forward_L{L}_2e21x85_counters.md")
     for r in (hbm, alu):
         r["traffic"] = traffic
     # the binding roof is the one the kernel is closer to

@@ -125,7 +125,7 @@ int fdas_make_templates(double zmax, double dz, int M, int L,
  * Sec. 3 / Sec. 4.2 (segment load with zero fill, forward FFT, K template
  * multiplies, inverse FFTs, |.|^2 and edge rejection) in one launch.
  *   spec_dev  : N complex bins, 8-byte aligned (read only);
- *   N         : bins, 0 <= N < 2^40 (N = 0 is a no-op);
+ *   N         : bins, 0 <= N <= 2^32 (N = 0 is a no-op);
  *   bank_dev  : prepared bank for (K, M, L) from fdas_prepare_bank;
  *   plane_dev : K*N floats, row-major [z][r], 4-byte aligned; every element
  *               is written.
@@ -142,6 +142,78 @@ int fdas_correlate(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf32 *bank_d
 int fdas_correlate_ex(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf32 *bank_dev,
                       int K, int M, int L, float *plane_dev, int zchunk,
                       hipStream_t stream);
+
+/* Bytes of device workspace fdas_correlate_batched needs for nspec spectra
+ * (the per-spectrum segment prefix sums), rounded up to 256. */
+size_t fdas_batched_workspace_bytes(int nspec);
+
+/*
+ * Batched ragged correlation: many spectra of uneven lengths (dedispersion
+ * trials x beams) against one shared bank in a single persistent launch.
+ * The paper processes independent time series one after another or one per
+ * GPU (Sec. 5.1, Sec. 6); here they share one launch so short spectra
+ * still fill the device.
+ *   specs_dev   : spectra packed back to back, 8-byte aligned; spectrum b is
+ *                 specs_dev[offsets[b] .. offsets[b+1]);
+ *   offsets_dev : DEVICE array of nspec + 1 int64, non-decreasing (a
+ *                 negative length is treated as empty); read at execution
+ *                 time, so a captured graph can be replayed for new batches
+ *                 after the caller rewrites offsets and spectra in place;
+ *   planes_dev  : plane b starts at planes_dev + K * offsets[b], layout
+ *                 [K][N_b] row-major (so K * offsets[nspec] floats in all);
+ *   ws_dev      : device workspace of ws_bytes >= fdas_batched_workspace_bytes
+ *                 (else FDAS_WORKSPACE_TOO_SMALL), 8-byte aligned; its
+ *                 contents are scratch.
+ * Results are bitwise identical to fdas_correlate on each spectrum with the
+ * same L.  nspec = 0 is a no-op.  Launches two kernels on `stream` and makes
+ * no host-side wait, allocation or memset, so it can be captured in a graph.
+ */
+int fdas_correlate_batched(const fdas_cf32 *specs_dev, const int64_t *offsets_dev, int nspec,
+                           const fdas_cf32 *bank_dev, int K, int M, int L, float *planes_dev,
+                           void *ws_dev, size_t ws_bytes, hipStream_t stream);
+
+/* Same with an explicit launch shape: zchunk templates per work item
+ * (0 = all K) and grid persistent workgroups (0 = fill the device). */
+int fdas_correlate_batched_ex(const fdas_cf32 *specs_dev, const int64_t *offsets_dev,
+                              int nspec, const fdas_cf32 *bank_dev, int K, int M, int L,
+                              float *planes_dev, int zchunk, int grid, void *ws_dev,
+                              size_t ws_bytes, hipStream_t stream);
+
+/* Bytes of device workspace for fdas_correlate_backward(_ex) with the same
+ * (N, K, M, L, zchunk; 0 = default), a multiple of 256; 0 for an invalid
+ * geometry.  Holds the per-window partial gradients:
+ * ceil(K/zchunk) * ceil(N/B) * L + ceil(N/B) * K * M complex values. */
+size_t fdas_backward_workspace_bytes(int64_t N, int K, int M, int L, int zchunk);
+
+/*
+ * Adjoint of fdas_correlate for the loss Lw = sum_{z,r} w[z][r] P[z][r]
+ * (not in the paper; derived from the definition in the header comment),
+ * in PyTorch's complex convention grad = dLw/dRe + i dLw/dIm.  With
+ * g[z][r] = 2 w[z][r] Y[z][r]:
+ *     grad_spec[k]    = sum_z sum_j T[z][j] g[z][k - e_j]
+ *     grad_taps[z][j] = sum_r conj(g[z][r]) A[r + e_j].
+ *   dLdP_dev      : w, K*N floats [z][r] (4-byte aligned);
+ *   grad_spec_dev : N complex outputs, or NULL to skip;
+ *   grad_taps_dev : K*M complex outputs, or NULL to skip (the templates
+ *                   enter through bank_dev, prepared from them);
+ *   ws_dev        : >= fdas_backward_workspace_bytes(N, K, M, L, 0) bytes,
+ *                   256-byte aligned; scratch.
+ * The complex plane Y is recomputed from the spectrum segment by segment,
+ * never stored.  The partial sums of every segment are reduced in FP64 in a
+ * fixed order, so results are deterministic.  Both gradients NULL is a
+ * no-op; N = 0 writes zero taps gradients.
+ */
+int fdas_correlate_backward(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf32 *bank_dev,
+                            int K, int M, int L, const float *dLdP_dev,
+                            fdas_cf32 *grad_spec_dev, fdas_cf32 *grad_taps_dev,
+                            void *ws_dev, size_t ws_bytes, hipStream_t stream);
+
+/* Same with an explicit number of templates per workgroup (0 = default);
+ * the workspace must be sized with the same zchunk. */
+int fdas_correlate_backward_ex(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf32 *bank_dev,
+                               int K, int M, int L, const float *dLdP_dev,
+                               fdas_cf32 *grad_spec_dev, fdas_cf32 *grad_taps_dev, int zchunk,
+                               void *ws_dev, size_t ws_bytes, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -10,9 +10,12 @@ There is no CPU fallback: if the library is missing, calls raise.
 """
 from __future__ import annotations
 
-from ._lib import (FdasError, fdas_bank_elems, fdas_correlate, fdas_correlate_ex,  # noqa: F401
-                   fdas_make_templates, fdas_make_templates_host, fdas_num_templates,
-                   fdas_prepare_bank, fdas_template_response, fdas_version, lib)
+from ._lib import (FdasError, fdas_backward_workspace_bytes, fdas_bank_elems,  # noqa: F401
+                   fdas_batched_workspace_bytes, fdas_correlate, fdas_correlate_backward,
+                   fdas_correlate_backward_ex, fdas_correlate_batched,
+                   fdas_correlate_batched_ex, fdas_correlate_ex, fdas_make_templates,
+                   fdas_make_templates_host, fdas_num_templates, fdas_prepare_bank,
+                   fdas_template_response, fdas_version, lib)
 
 
 def make_bank(zmax: float, dz: float, M: int, L: int, device="cuda"):
@@ -42,3 +45,37 @@ def correlate(spec, bank, K: int, M: int, L: int, plane=None, zchunk: int = 0):
         plane = torch.empty((K, N), dtype=torch.float32, device=spec.device)
     fdas_correlate_ex(spec, N, bank, K, M, L, plane, zchunk)
     return plane
+
+
+def pack(spectra, device="cuda"):
+    """Pack a list of 1-D complex64 spectra: (specs, offsets[nspec+1] int64)."""
+    import torch
+    lens = [int(s.numel()) for s in spectra]
+    offs = torch.zeros(len(lens) + 1, dtype=torch.int64)
+    if lens:
+        offs[1:] = torch.cumsum(torch.tensor(lens, dtype=torch.int64), 0)
+    specs = torch.cat([s.reshape(-1).to(device) for s in spectra]) if spectra else \
+        torch.zeros(0, dtype=torch.complex64, device=device)
+    return specs.contiguous(), offs.to(device)
+
+
+def correlate_batched(specs, offsets, bank, K: int, M: int, L: int, planes=None, ws=None,
+                      zchunk: int = 0, grid: int = 0):
+    """Planes of packed spectra in one persistent launch.
+
+    ``offsets`` is the device int64 tensor of nspec + 1 offsets; plane b is
+    ``planes[K*offsets[b] : K*offsets[b+1]].view(K, N_b)``.  ``planes`` and
+    the workspace ``ws`` are allocated when not given (pass them to keep the
+    call allocation-free, e.g. under graph capture).
+    """
+    import torch
+    from ._lib import fdas_batched_workspace_bytes, fdas_correlate_batched_ex
+    nspec = offsets.numel() - 1
+    if planes is None:
+        total = int(offsets[-1].item()) if nspec >= 0 else 0
+        planes = torch.empty(K * total, dtype=torch.float32, device=specs.device)
+    if ws is None:
+        ws = torch.empty(max(fdas_batched_workspace_bytes(nspec), 1), dtype=torch.uint8,
+                         device=specs.device)
+    fdas_correlate_batched_ex(specs, offsets, nspec, bank, K, M, L, planes, zchunk, grid, ws)
+    return planes

@@ -38,6 +38,12 @@ SIGNATURES = [
     ("fdas_make_templates", _I, [_D, _D, _I, _I, _P, _P, _P]),
     ("fdas_correlate", _I, [_P, _I64, _P, _I, _I, _I, _P, _P]),
     ("fdas_correlate_ex", _I, [_P, _I64, _P, _I, _I, _I, _P, _I, _P]),
+    ("fdas_batched_workspace_bytes", _SZ, [_I]),
+    ("fdas_correlate_batched", _I, [_P, _P, _I, _P, _I, _I, _I, _P, _P, _SZ, _P]),
+    ("fdas_correlate_batched_ex", _I, [_P, _P, _I, _P, _I, _I, _I, _P, _I, _I, _P, _SZ, _P]),
+    ("fdas_backward_workspace_bytes", _SZ, [_I64, _I, _I, _I, _I]),
+    ("fdas_correlate_backward", _I, [_P, _I64, _P, _I, _I, _I, _P, _P, _P, _P, _SZ, _P]),
+    ("fdas_correlate_backward_ex", _I, [_P, _I64, _P, _I, _I, _I, _P, _P, _P, _I, _P, _SZ, _P]),
 ]
 
 
@@ -171,3 +177,52 @@ def fdas_correlate_ex(spec, N: int, bank, K: int, M: int, L: int, plane, zchunk:
     _require(plane, torch.float32, "plane", K * N)
     _check(lib().fdas_correlate_ex(_ptr(spec), N, _ptr(bank), K, M, L, _ptr(plane), zchunk,
                                    _stream(stream, spec)), "fdas_correlate_ex")
+
+
+def fdas_batched_workspace_bytes(nspec: int) -> int:
+    return int(lib().fdas_batched_workspace_bytes(nspec))
+
+
+def fdas_correlate_batched(specs, offsets, nspec: int, bank, K: int, M: int, L: int, planes,
+                           ws, stream=None) -> None:
+    fdas_correlate_batched_ex(specs, offsets, nspec, bank, K, M, L, planes, 0, 0, ws, stream)
+
+
+def fdas_correlate_batched_ex(specs, offsets, nspec: int, bank, K: int, M: int, L: int, planes,
+                              zchunk: int, grid: int, ws, stream=None) -> None:
+    import torch
+    _require(specs, torch.complex64, "specs")
+    _require(offsets, torch.int64, "offsets", nspec + 1)
+    _require(bank, torch.complex64, "bank", fdas_bank_elems(K, L))
+    _require(planes, torch.float32, "planes")
+    _require(ws, torch.uint8, "ws", fdas_batched_workspace_bytes(nspec))
+    _check(lib().fdas_correlate_batched_ex(_ptr(specs), _ptr(offsets), nspec, _ptr(bank), K, M, L,
+                                           _ptr(planes), zchunk, grid, _ptr(ws),
+                                           ws.numel(), _stream(stream, specs)),
+           "fdas_correlate_batched")
+
+
+def fdas_backward_workspace_bytes(N: int, K: int, M: int, L: int, zchunk: int = 0) -> int:
+    return int(lib().fdas_backward_workspace_bytes(N, K, M, L, zchunk))
+
+
+def fdas_correlate_backward(spec, N: int, bank, K: int, M: int, L: int, dLdP, grad_spec,
+                            grad_taps, ws, stream=None) -> None:
+    fdas_correlate_backward_ex(spec, N, bank, K, M, L, dLdP, grad_spec, grad_taps, 0, ws, stream)
+
+
+def fdas_correlate_backward_ex(spec, N: int, bank, K: int, M: int, L: int, dLdP, grad_spec,
+                               grad_taps, zchunk: int, ws, stream=None) -> None:
+    import torch
+    _require(spec, torch.complex64, "spec", N)
+    _require(bank, torch.complex64, "bank", fdas_bank_elems(K, L))
+    _require(dLdP, torch.float32, "dLdP", K * N)
+    if grad_spec is not None:
+        _require(grad_spec, torch.complex64, "grad_spec", N)
+    if grad_taps is not None:
+        _require(grad_taps, torch.complex64, "grad_taps", K * M)
+    _require(ws, torch.uint8, "ws", fdas_backward_workspace_bytes(N, K, M, L, zchunk))
+    _check(lib().fdas_correlate_backward_ex(_ptr(spec), N, _ptr(bank), K, M, L, _ptr(dLdP),
+                                            _ptr(grad_spec), _ptr(grad_taps), zchunk, _ptr(ws),
+                                            ws.numel(), _stream(stream, spec)),
+           "fdas_correlate_backward")

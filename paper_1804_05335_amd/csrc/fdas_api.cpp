@@ -42,6 +42,7 @@ bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
 constexpr int kMaxK = 4096;
 constexpr int64_t kMaxN = int64_t(1) << 32;
+constexpr int kMaxSpectra = 1 << 24;
 
 int check_grid(double zmax, double dz, int* K)
 {
@@ -237,6 +238,143 @@ int fdas_correlate(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* bank_d
                    int L, float* plane_dev, hipStream_t stream)
 {
     return fdas_correlate_ex(spec_dev, N, bank_dev, K, M, L, plane_dev, 0, stream);
+}
+
+size_t fdas_batched_workspace_bytes(int nspec)
+{
+    if (nspec < 0)
+        return 0;
+    const size_t b = sizeof(int64_t) * ((size_t)nspec + 1);
+    return (b + 255) & ~(size_t)255;
+}
+
+int fdas_correlate_batched_ex(const fdas_cf32* specs_dev, const int64_t* offsets_dev, int nspec,
+                              const fdas_cf32* bank_dev, int K, int M, int L, float* planes_dev,
+                              int zchunk, int grid, void* ws_dev, size_t ws_bytes,
+                              hipStream_t stream)
+{
+    int st = check_geometry(K, M, L);
+    if (st)
+        return st;
+    if (nspec < 0 || nspec > kMaxSpectra)
+        return fail(FDAS_INVALID_ARG, "nspec = %d outside [0, %d]", nspec, kMaxSpectra);
+    if (zchunk < 0 || zchunk > K)
+        return fail(FDAS_INVALID_ARG, "zchunk = %d outside [0, K = %d]", zchunk, K);
+    if (grid < 0 || grid > (1 << 20))
+        return fail(FDAS_INVALID_ARG, "grid = %d outside [0, 2^20]", grid);
+    if (nspec == 0)
+        return ok();
+    if (!specs_dev || !offsets_dev || !bank_dev || !planes_dev || !ws_dev)
+        return fail(FDAS_INVALID_ARG, "specs, offsets, bank, planes and ws must not be NULL");
+    if (!aligned(specs_dev, 8) || !aligned(offsets_dev, 8) || !aligned(bank_dev, 16) ||
+        !aligned(planes_dev, 4) || !aligned(ws_dev, 8))
+        return fail(FDAS_INVALID_ARG,
+                    "misaligned pointer (specs 8 B, offsets 8 B, bank 16 B, planes 4 B, ws 8 B)");
+    if (ws_bytes < fdas_batched_workspace_bytes(nspec))
+        return fail(FDAS_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", ws_bytes,
+                    fdas_batched_workspace_bytes(nspec));
+    if (zchunk == 0)
+        zchunk = K;
+    hipError_t e = fdas::launch_batched(reinterpret_cast<const float2*>(specs_dev), offsets_dev,
+                                        nspec, reinterpret_cast<const float2*>(bank_dev), K, M,
+                                        L, planes_dev, zchunk, static_cast<int64_t*>(ws_dev),
+                                        grid, stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "batched launch");
+    return ok();
+}
+
+int fdas_correlate_batched(const fdas_cf32* specs_dev, const int64_t* offsets_dev, int nspec,
+                           const fdas_cf32* bank_dev, int K, int M, int L, float* planes_dev,
+                           void* ws_dev, size_t ws_bytes, hipStream_t stream)
+{
+    return fdas_correlate_batched_ex(specs_dev, offsets_dev, nspec, bank_dev, K, M, L,
+                                     planes_dev, 0, 0, ws_dev, ws_bytes, stream);
+}
+
+namespace {
+
+int backward_zchunk(int64_t nwin, int K, int zchunk)
+{
+    if (zchunk > 0)
+        return zchunk;
+    // enough workgroups to fill the device; each chunk adds one partial
+    // gradient window and one recomputed forward FFT per window
+    int64_t chunks = (2048 + (nwin > 0 ? nwin : 1) - 1) / (nwin > 0 ? nwin : 1);
+    if (chunks < 1) chunks = 1;
+    if (chunks > K) chunks = K;
+    return (int)((K + chunks - 1) / chunks);
+}
+
+void backward_layout(int64_t N, int K, int M, int L, int zchunk, size_t* offT, size_t* total)
+{
+    const int64_t nwin = (N + (L - M) - 1) / (L - M);
+    const int zc = backward_zchunk(nwin, K, zchunk);
+    const int64_t nzc = (K + zc - 1) / zc;
+    const size_t a = (size_t)nzc * (size_t)nwin * (size_t)L * sizeof(fdas_cf32);
+    const size_t t = (size_t)nwin * (size_t)K * (size_t)M * sizeof(fdas_cf32);
+    *offT = (a + 255) & ~(size_t)255;
+    *total = ((*offT + t) + 255) & ~(size_t)255;
+}
+
+}  // namespace
+
+size_t fdas_backward_workspace_bytes(int64_t N, int K, int M, int L, int zchunk)
+{
+    if (N < 0 || N > kMaxN || check_geometry(K, M, L) != FDAS_OK || zchunk < 0 || zchunk > K)
+        return 0;
+    size_t offT = 0, total = 0;
+    backward_layout(N, K, M, L, zchunk, &offT, &total);
+    return total < 256 ? 256 : total;
+}
+
+int fdas_correlate_backward_ex(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* bank_dev,
+                               int K, int M, int L, const float* dLdP_dev,
+                               fdas_cf32* grad_spec_dev, fdas_cf32* grad_taps_dev, int zchunk,
+                               void* ws_dev, size_t ws_bytes, hipStream_t stream)
+{
+    int st = check_geometry(K, M, L);
+    if (st)
+        return st;
+    if (N < 0 || N > kMaxN)
+        return fail(FDAS_INVALID_ARG, "N = %lld outside [0, 2^32]", (long long)N);
+    if (zchunk < 0 || zchunk > K)
+        return fail(FDAS_INVALID_ARG, "zchunk = %d outside [0, K = %d]", zchunk, K);
+    if (!grad_spec_dev && !grad_taps_dev)
+        return ok();
+    if (!bank_dev || !ws_dev || (N > 0 && (!spec_dev || !dLdP_dev)))
+        return fail(FDAS_INVALID_ARG, "spec, bank, dLdP and ws must not be NULL");
+    if ((spec_dev && !aligned(spec_dev, 8)) || !aligned(bank_dev, 16) ||
+        (dLdP_dev && !aligned(dLdP_dev, 4)) || (grad_spec_dev && !aligned(grad_spec_dev, 8)) ||
+        (grad_taps_dev && !aligned(grad_taps_dev, 8)) || !aligned(ws_dev, 256))
+        return fail(FDAS_INVALID_ARG,
+                    "misaligned pointer (spec/grads 8 B, bank 16 B, dLdP 4 B, ws 256 B)");
+    const size_t need = fdas_backward_workspace_bytes(N, K, M, L, zchunk);
+    if (ws_bytes < need)
+        return fail(FDAS_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", ws_bytes,
+                    need);
+    const int64_t nwin = (N + (L - M) - 1) / (L - M);
+    const int zc = backward_zchunk(nwin, K, zchunk);
+    size_t offT = 0, total = 0;
+    backward_layout(N, K, M, L, zchunk, &offT, &total);
+    auto* base = static_cast<unsigned char*>(ws_dev);
+    hipError_t e = fdas::launch_backward(
+        reinterpret_cast<const float2*>(spec_dev), N, reinterpret_cast<const float2*>(bank_dev),
+        K, M, L, dLdP_dev, reinterpret_cast<float2*>(grad_spec_dev),
+        reinterpret_cast<float2*>(grad_taps_dev), zc, reinterpret_cast<float2*>(base),
+        reinterpret_cast<float2*>(base + offT), stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "backward launch");
+    return ok();
+}
+
+int fdas_correlate_backward(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* bank_dev, int K,
+                            int M, int L, const float* dLdP_dev, fdas_cf32* grad_spec_dev,
+                            fdas_cf32* grad_taps_dev, void* ws_dev, size_t ws_bytes,
+                            hipStream_t stream)
+{
+    return fdas_correlate_backward_ex(spec_dev, N, bank_dev, K, M, L, dLdP_dev, grad_spec_dev,
+                                      grad_taps_dev, 0, ws_dev, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -2,6 +2,7 @@
 // overlap-save correlation (Sec. 3, Fig. 1; Sec. 4.2).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 
 #include "fdas_fft.hpp"
@@ -66,74 +67,330 @@ hipError_t launch_prepare_bank(const float2* taps, int K, int M, int L, float2* 
 
 // ---- fused forward correlation ---------------------------------------------
 //
-// One workgroup per (segment s, chunk of templates).  Segment s produces the
-// B = L - M outputs [s B, s B + B) from the window of input bins
-// [s B - M/2, s B - M/2 + L) (zero outside [0, N)).  Per workgroup:
+// One work item = (segment s of a spectrum, chunk [z0, z1) of templates).
+// Segment s produces the B = L - M outputs [s B, s B + B) from the window
+// of input bins [s B - M/2, s B - M/2 + L) (zero outside [0, N)):
 //   1. coalesced window load (lane t: positions t + T m);
 //   2. forward FFT of the window (kept in registers for all templates);
 //   3. for each template z of the chunk: multiply by H_z (natural order,
 //      next H_z prefetched), inverse FFT, |.|^2, and non-temporal stores of
 //      the B valid outputs to plane[z][s B + u].
 // Nothing but the valid plane values reaches HBM (Sec. 4.2 first paragraph).
+// The LDS ping-pong buffers la/lb keep alternating across calls, so
+// consecutive work items of one workgroup need no extra barrier.
 template <int L>
-__global__ __launch_bounds__(L / Geometry<L>::E) void forward_kernel(
-    const float2* __restrict__ spec, int64_t N, const float2* __restrict__ bank, int K, int M,
-    int zchunk, float* __restrict__ plane)
-{
-    constexpr int E = Geometry<L>::E;
+struct Fwd {
+    static constexpr int E = Geometry<L>::E;
     using F = FFT<L, E, typename Geometry<L>::R>;
-    constexpr int T = F::T;
-    __shared__ float2 lds[2][LdsSize<L>::value];
+    static constexpr int T = F::T;
+    static constexpr int NTW = F::NTW;
 
-    const int t = threadIdx.x;
-    const int B = L - M;
-    const int64_t s = blockIdx.x;
-    const int64_t out0 = s * B;
-    const int64_t in0 = out0 - M / 2;
-    const int z0 = blockIdx.y * zchunk;
-    const int z1 = min(K, z0 + zchunk);
-
-    float2 tw[F::NTW];
-    F::twiddles(tw, bank + (int64_t)K * L, t);
-
-    float2 X[E];
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-        const int64_t idx = in0 + t + T * m;
-        X[m] = (idx >= 0 && idx < N) ? spec[idx] : make_float2(0.f, 0.f);
-    }
-    float2* la = lds[0];
-    float2* lb = lds[1];
-    F::template run<false>(X, la, lb, tw, t);
-
-    float2 H[E];
+    __device__ static void item(const float2* __restrict__ spec, int64_t N,
+                                const float2* __restrict__ bank, int M, int64_t s, int z0,
+                                int z1, float* __restrict__ plane, const float2 (&tw)[NTW],
+                                float2*& la, float2*& lb, int t)
     {
-        const float2* hz = bank + (int64_t)z0 * L + t;
+        const int B = L - M;
+        const int64_t out0 = s * B;
+        const int64_t in0 = out0 - M / 2;
+
+        float2 X[E];
 #pragma unroll
-        for (int m = 0; m < E; ++m)
-            H[m] = hz[T * m];
-    }
-    for (int z = z0; z < z1; ++z) {
-        float2 v[E];
-#pragma unroll
-        for (int m = 0; m < E; ++m)
-            v[m] = cmul(X[m], H[m]);
-        if (z + 1 < z1) {
-            const float2* hz = bank + (int64_t)(z + 1) * L + t;
+        for (int m = 0; m < E; ++m) {
+            const int64_t idx = in0 + t + T * m;
+            X[m] = (idx >= 0 && idx < N) ? spec[idx] : make_float2(0.f, 0.f);
+        }
+        F::template run<false>(X, la, lb, tw, t);
+
+        float2 H[E];
+        {
+            const float2* hz = bank + (int64_t)z0 * L + t;
 #pragma unroll
             for (int m = 0; m < E; ++m)
                 H[m] = hz[T * m];
         }
-        F::template run<true>(v, la, lb, tw, t);
-        float* row = plane + (int64_t)z * N + out0;
+        for (int z = z0; z < z1; ++z) {
+            float2 v[E];
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const int u = t + T * m - M / 2;
-            if (u >= 0 && u < B && out0 + u < N) {
-                const float p = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
-                __builtin_nontemporal_store(p, row + u);
+            for (int m = 0; m < E; ++m)
+                v[m] = cmul(X[m], H[m]);
+            if (z + 1 < z1) {
+                const float2* hz = bank + (int64_t)(z + 1) * L + t;
+#pragma unroll
+                for (int m = 0; m < E; ++m)
+                    H[m] = hz[T * m];
+            }
+            F::template run<true>(v, la, lb, tw, t);
+            float* row = plane + (int64_t)z * N + out0;
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int u = t + T * m - M / 2;
+                if (u >= 0 && u < B && out0 + u < N) {
+                    const float p = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
+                    __builtin_nontemporal_store(p, row + u);
+                }
             }
         }
+    }
+};
+
+// One spectrum: grid (segments, template chunks).
+template <int L>
+__global__ __launch_bounds__(Fwd<L>::T) void forward_kernel(
+    const float2* __restrict__ spec, int64_t N, const float2* __restrict__ bank, int K, int M,
+    int zchunk, float* __restrict__ plane)
+{
+    using W = Fwd<L>;
+    __shared__ float2 lds[2][LdsSize<L>::value];
+    const int t = threadIdx.x;
+    float2 tw[W::NTW];
+    W::F::twiddles(tw, bank + (int64_t)K * L, t);
+    float2* la = lds[0];
+    float2* lb = lds[1];
+    const int z0 = blockIdx.y * zchunk;
+    const int z1 = min(K, z0 + zchunk);
+    W::item(spec, N, bank, M, blockIdx.x, z0, z1, plane, tw, la, lb, t);
+}
+
+// ---- adjoint (backward) ------------------------------------------------------
+//
+// Loss Lw = sum_{z,r} w[z][r] P[z][r] with w = dLw/dP given.  In PyTorch's
+// complex convention (grad = dLw/dRe + i dLw/dIm), with g = 2 w Y:
+//   grad_A[k]    = sum_z sum_j T[z][j] g[z][k - e_j]
+//   grad_T[z][j] = sum_r conj(g[z][r]) A[r + e_j].
+// Per forward window s (input bins [w0, w0 + L), w0 = s B - M/2; owned outputs
+// t in [M/2, M/2 + B)), the correlation is y = IFFT(X H_z) with X = FFT(a_w);
+// its adjoint is IFFT(conj(H_z) FFT(g_w)), and the window's part of grad_T is
+// the circular cross-correlation IFFT(conj(G) X)/L at lags e_j.  Because g_w
+// is supported on the owned outputs only, neither wraps, and summing the
+// windows' contributions gives the exact gradients.  Y is recomputed, never
+// stored.  Window contributions go to per-(chunk, window) partial buffers and
+// are summed in FP64, in a fixed order, by the two reduction kernels.
+template <int L>
+struct Bwd {
+    using W = Fwd<L>;
+    using F = typename W::F;
+    static constexpr int E = W::E;
+    static constexpr int T = W::T;
+    static constexpr int NTW = W::NTW;
+
+    __device__ static void item(const float2* __restrict__ spec, int64_t N,
+                                const float2* __restrict__ bank, int M, int64_t s, int z0,
+                                int z1, const float* __restrict__ dLdP, bool want_A,
+                                bool want_T, float2* __restrict__ partA,
+                                float2* __restrict__ partT, const float2 (&tw)[NTW],
+                                float2*& la, float2*& lb, int t)
+    {
+        const int B = L - M;
+        const int64_t out0 = s * B;
+        const int64_t in0 = out0 - M / 2;
+
+        float2 X[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int64_t idx = in0 + t + T * m;
+            X[m] = (idx >= 0 && idx < N) ? spec[idx] : make_float2(0.f, 0.f);
+        }
+        F::template run<false>(X, la, lb, tw, t);
+
+        float2 acc[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            acc[m] = make_float2(0.f, 0.f);
+
+        for (int z = z0; z < z1; ++z) {
+            const float2* hz = bank + (int64_t)z * L + t;
+            float2 v[E];
+#pragma unroll
+            for (int m = 0; m < E; ++m)
+                v[m] = cmul(X[m], hz[T * m]);
+            F::template run<true>(v, la, lb, tw, t);
+            // g = 2 w y on the owned outputs, zero elsewhere
+            const float* wz = dLdP + (int64_t)z * N + out0;
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int u = t + T * m - M / 2;
+                float wv = 0.f;
+                if (u >= 0 && u < B && out0 + u < N)
+                    wv = 2.f * wz[u];
+                v[m] = make_float2(wv * v[m].x, wv * v[m].y);
+            }
+            F::template run<false>(v, la, lb, tw, t);
+            if (want_A) {
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const float2 c = cmulc(v[m], hz[T * m]);
+                    acc[m] = cadd(acc[m], c);
+                }
+            }
+            if (want_T) {
+#pragma unroll
+                for (int m = 0; m < E; ++m)
+                    v[m] = cmulc(X[m], v[m]);          // X conj(G)
+                F::template run<true>(v, la, lb, tw, t);
+                float2* pz = partT + (int64_t)z * M;
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int p = t + T * m;
+                    if (p < M / 2)
+                        pz[p + M / 2] = v[m];
+                    else if (p >= L - M / 2)
+                        pz[p - L + M / 2] = v[m];
+                }
+            }
+        }
+        if (want_A) {
+            F::template run<true>(acc, la, lb, tw, t);
+#pragma unroll
+            for (int m = 0; m < E; ++m)
+                partA[t + T * m] = acc[m];
+        }
+    }
+};
+
+template <int L>
+__global__ __launch_bounds__(Fwd<L>::T) void backward_kernel(
+    const float2* __restrict__ spec, int64_t N, const float2* __restrict__ bank, int K, int M,
+    int zchunk, int64_t nwin, const float* __restrict__ dLdP, int want_A, int want_T,
+    float2* __restrict__ partA, float2* __restrict__ partT)
+{
+    using Bk = Bwd<L>;
+    __shared__ float2 lds[2][LdsSize<L>::value];
+    const int t = threadIdx.x;
+    float2 tw[Bk::NTW];
+    Bk::F::twiddles(tw, bank + (int64_t)K * L, t);
+    float2* la = lds[0];
+    float2* lb = lds[1];
+    const int64_t s = blockIdx.x;
+    const int c = blockIdx.y;
+    const int z0 = c * zchunk;
+    const int z1 = min(K, z0 + zchunk);
+    Bk::item(spec, N, bank, M, s, z0, z1, dLdP, want_A != 0, want_T != 0,
+             partA + ((int64_t)c * nwin + s) * L, partT + s * (int64_t)K * M, tw, la, lb, t);
+}
+
+// grad_A[k] = sum over chunks c and windows s covering k of
+// partA[c][s][k - (s B - M/2)], summed in FP64 in (c, s) order.
+__global__ void reduce_grad_spec_kernel(const float2* __restrict__ partA, int64_t N, int L, int M,
+                                        int64_t nwin, int nzc, float2* __restrict__ grad)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N)
+        return;
+    const int B = L - M;
+    const int64_t hi_num = k + M / 2;
+    int64_t s_hi = hi_num / B;
+    if (s_hi > nwin - 1)
+        s_hi = nwin - 1;
+    const int64_t lo_num = k + M / 2 - L;     // windows with s B - M/2 + L > k
+    const int64_t s_lo = lo_num < 0 ? 0 : lo_num / B + 1;
+    double sr = 0.0, si = 0.0;
+    for (int c = 0; c < nzc; ++c)
+        for (int64_t s = s_lo; s <= s_hi; ++s) {
+            const int64_t p = k - (s * B - M / 2);
+            const float2 v = partA[((int64_t)c * nwin + s) * L + p];
+            sr += v.x;
+            si += v.y;
+        }
+    grad[k] = make_float2((float)sr, (float)si);
+}
+
+// grad_T[z][j] = (1/L) sum_s partT[s][z][j], FP64 in window order.
+__global__ void reduce_grad_taps_kernel(const float2* __restrict__ partT, int64_t nwin, int KM,
+                                        int L, float2* __restrict__ grad)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= KM)
+        return;
+    double sr = 0.0, si = 0.0;
+    for (int64_t s = 0; s < nwin; ++s) {
+        const float2 v = partT[s * KM + i];
+        sr += v.x;
+        si += v.y;
+    }
+    const double inv = 1.0 / (double)L;
+    grad[i] = make_float2((float)(sr * inv), (float)(si * inv));
+}
+
+// ---- batched ragged correlation --------------------------------------------
+//
+// Spectra b = 0..nspec-1 are packed back to back: spectrum b is
+// specs[offsets[b] .. offsets[b+1]) and its plane starts at
+// planes + K * offsets[b] ([K][N_b] row-major).  A single-workgroup scan
+// turns the lengths into segment counts and their prefix sums segpre[0..nspec]
+// (segpre[nspec] = total segments); the persistent kernel then walks the work
+// items (tile, template chunk) with a grid-stride loop, so one launch of a
+// fixed grid covers any batch and every wave reaches the loop's end.
+
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void segment_scan_kernel(
+    const int64_t* __restrict__ offsets, int nspec, int B, int64_t* __restrict__ segpre)
+{
+    __shared__ int64_t part[kScanThreads];
+    __shared__ int64_t carry;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        carry = 0;
+        segpre[0] = 0;
+    }
+    __syncthreads();
+    for (int base = 0; base < nspec; base += kScanThreads) {
+        const int b = base + t;
+        int64_t segs = 0;
+        if (b < nspec) {
+            const int64_t n = offsets[b + 1] - offsets[b];
+            segs = n > 0 ? (n + B - 1) / B : 0;
+        }
+        part[t] = segs;
+        __syncthreads();
+        // Hillis-Steele inclusive scan over the chunk
+        for (int d = 1; d < kScanThreads; d <<= 1) {
+            const int64_t add = t >= d ? part[t - d] : 0;
+            __syncthreads();
+            part[t] += add;
+            __syncthreads();
+        }
+        if (b < nspec)
+            segpre[b + 1] = carry + part[t];
+        __syncthreads();
+        if (t == kScanThreads - 1)
+            carry += part[t];
+        __syncthreads();
+    }
+}
+
+template <int L>
+__global__ __launch_bounds__(Fwd<L>::T) void batched_kernel(
+    const float2* __restrict__ specs, const int64_t* __restrict__ offsets,
+    const int64_t* __restrict__ segpre, int nspec, const float2* __restrict__ bank, int K,
+    int M, int zchunk, float* __restrict__ planes)
+{
+    using W = Fwd<L>;
+    __shared__ float2 lds[2][LdsSize<L>::value];
+    const int t = threadIdx.x;
+    float2 tw[W::NTW];
+    W::F::twiddles(tw, bank + (int64_t)K * L, t);
+    float2* la = lds[0];
+    float2* lb = lds[1];
+    const int nzc = (K + zchunk - 1) / zchunk;
+    const int64_t total = segpre[nspec] * nzc;
+    for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+        const int64_t tile = it / nzc;
+        const int zc = (int)(it - tile * nzc);
+        // spectrum b: the last index with segpre[b] <= tile
+        int lo = 0, hi = nspec - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (segpre[mid] <= tile) lo = mid; else hi = mid - 1;
+        }
+        const int b = lo;
+        const int64_t off = offsets[b];
+        const int64_t Nb = offsets[b + 1] - off;
+        const int z0 = zc * zchunk;
+        const int z1 = min(K, z0 + zchunk);
+        W::item(specs + off, Nb, bank, M, tile - segpre[b], z0, z1, planes + (int64_t)K * off,
+                tw, la, lb, t);
     }
 }
 
@@ -156,7 +413,7 @@ static hipError_t launch_forward_L(const float2* spec, int64_t N, const float2* 
     const int64_t nseg = (N + B - 1) / B;
     const int nzc = (K + zchunk - 1) / zchunk;
     dim3 grid((unsigned)nseg, (unsigned)nzc);
-    hipLaunchKernelGGL(forward_kernel<L>, grid, dim3(L / Geometry<L>::E), 0, s, spec, N, bank,
+    hipLaunchKernelGGL(forward_kernel<L>, grid, dim3(Fwd<L>::T), 0, s, spec, N, bank,
                        K, M, zchunk, plane);
     return hipGetLastError();
 }
@@ -173,6 +430,124 @@ hipError_t launch_forward(const float2* spec, int64_t N, const float2* bank, int
     case 8192: return launch_forward_L<8192>(spec, N, bank, K, M, plane, zchunk, s);
     default:   return hipErrorInvalidValue;
     }
+}
+
+// Persistent grid: resident workgroups per CU x CUs, queried once per
+// (device, L) and cached, so later calls (e.g. under graph capture) make no
+// runtime queries.
+template <int L>
+static hipError_t full_grid(int* grid)
+{
+    constexpr int kMaxDev = 64;
+    static std::atomic<int> cache[kMaxDev];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev >= 0 && dev < kMaxDev) {
+        const int c = cache[dev].load(std::memory_order_relaxed);
+        if (c > 0) {
+            *grid = c;
+            return hipSuccess;
+        }
+    }
+    int per_cu = 0, cus = 0;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel<L>, Fwd<L>::T,
+                                                          0)) != hipSuccess)
+        return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
+        hipSuccess)
+        return e;
+    *grid = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+    if (dev >= 0 && dev < kMaxDev)
+        cache[dev].store(*grid, std::memory_order_relaxed);
+    return hipSuccess;
+}
+
+template <int L>
+static hipError_t launch_batched_L(const float2* specs, const int64_t* offsets, int nspec,
+                                   const float2* bank, int K, int M, float* planes, int zchunk,
+                                   int64_t* segpre, int grid, hipStream_t s)
+{
+    if (grid <= 0) {
+        hipError_t e = full_grid<L>(&grid);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(batched_kernel<L>, dim3(grid), dim3(Fwd<L>::T), 0, s, specs, offsets,
+                       segpre, nspec, bank, K, M, zchunk, planes);
+    return hipGetLastError();
+}
+
+hipError_t launch_batched(const float2* specs, const int64_t* offsets, int nspec,
+                          const float2* bank, int K, int M, int L, float* planes, int zchunk,
+                          int64_t* segpre, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(segment_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, offsets, nspec,
+                       L - M, segpre);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    switch (L) {
+    case 256:  return launch_batched_L<256>(specs, offsets, nspec, bank, K, M, planes, zchunk, segpre, grid, s);
+    case 512:  return launch_batched_L<512>(specs, offsets, nspec, bank, K, M, planes, zchunk, segpre, grid, s);
+    case 1024: return launch_batched_L<1024>(specs, offsets, nspec, bank, K, M, planes, zchunk, segpre, grid, s);
+    case 2048: return launch_batched_L<2048>(specs, offsets, nspec, bank, K, M, planes, zchunk, segpre, grid, s);
+    case 4096: return launch_batched_L<4096>(specs, offsets, nspec, bank, K, M, planes, zchunk, segpre, grid, s);
+    case 8192: return launch_batched_L<8192>(specs, offsets, nspec, bank, K, M, planes, zchunk, segpre, grid, s);
+    default:   return hipErrorInvalidValue;
+    }
+}
+
+template <int L>
+static hipError_t launch_backward_L(const float2* spec, int64_t N, const float2* bank, int K,
+                                   int M, int zchunk, int64_t nwin, const float* dLdP,
+                                   int want_A, int want_T, float2* partA, float2* partT,
+                                   hipStream_t s)
+{
+    const int nzc = (K + zchunk - 1) / zchunk;
+    hipLaunchKernelGGL(backward_kernel<L>, dim3((unsigned)nwin, (unsigned)nzc), dim3(Fwd<L>::T),
+                       0, s, spec, N, bank, K, M, zchunk, nwin, dLdP, want_A, want_T, partA,
+                       partT);
+    return hipGetLastError();
+}
+
+hipError_t launch_backward(const float2* spec, int64_t N, const float2* bank, int K, int M,
+                          int L, const float* dLdP, float2* grad_spec, float2* grad_taps,
+                          int zchunk, float2* partA, float2* partT, hipStream_t s)
+{
+    const int64_t nwin = (N + (L - M) - 1) / (L - M);
+    const int want_A = grad_spec != nullptr, want_T = grad_taps != nullptr;
+    hipError_t e = hipSuccess;
+    if (nwin > 0) {
+    switch (L) {
+    case 256:  e = launch_backward_L<256>(spec, N, bank, K, M, zchunk, nwin, dLdP, want_A, want_T, partA, partT, s); break;
+    case 512:  e = launch_backward_L<512>(spec, N, bank, K, M, zchunk, nwin, dLdP, want_A, want_T, partA, partT, s); break;
+    case 1024: e = launch_backward_L<1024>(spec, N, bank, K, M, zchunk, nwin, dLdP, want_A, want_T, partA, partT, s); break;
+    case 2048: e = launch_backward_L<2048>(spec, N, bank, K, M, zchunk, nwin, dLdP, want_A, want_T, partA, partT, s); break;
+    case 4096: e = launch_backward_L<4096>(spec, N, bank, K, M, zchunk, nwin, dLdP, want_A, want_T, partA, partT, s); break;
+    case 8192: e = launch_backward_L<8192>(spec, N, bank, K, M, zchunk, nwin, dLdP, want_A, want_T, partA, partT, s); break;
+    default:   return hipErrorInvalidValue;
+    }
+    }
+    if (e != hipSuccess)
+        return e;
+    const int bs = 256;
+    if (want_A && N > 0) {
+        const int nzc = (K + zchunk - 1) / zchunk;
+        hipLaunchKernelGGL(reduce_grad_spec_kernel, dim3((unsigned)((N + bs - 1) / bs)), dim3(bs),
+                           0, s, partA, N, L, M, nwin, nzc, grad_spec);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+    }
+    if (want_T) {
+        const int KM = K * M;
+        hipLaunchKernelGGL(reduce_grad_taps_kernel, dim3((KM + bs - 1) / bs), dim3(bs), 0, s,
+                           partT, nwin, KM, L, grad_taps);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace fdas

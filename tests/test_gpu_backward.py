@@ -1,0 +1,140 @@
+"""GPU checks of the adjoint kernels (gradients of Lw = sum w P).
+
+Against the FP64 oracle gradients (themselves pinned by central finite
+differences), to 1e-5 of the largest gradient component; directly against
+FP64 finite differences of the oracle loss on a 4096-bin slice of the
+2^20-bin workload with 9 templates; and at the full 2^20-bin, 85 x 128-tap
+workload.
+"""
+import numpy as np
+import pytest
+
+import fdas_synth as syn
+from oracle import direct, native
+from oracle import templates as ot
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def fd():
+    import paper_1804_05335_amd as f
+    f.lib()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return f
+
+
+def _grads(fd, A, taps, w, L, want=(True, True), zchunk=0):
+    K, M = taps.shape
+    N = len(A)
+    spec = torch.from_numpy(np.ascontiguousarray(A, dtype=np.complex64)).cuda()
+    tt = torch.from_numpy(np.ascontiguousarray(taps, dtype=np.complex64)).cuda()
+    bank = fd.prepare_bank(tt, L)
+    wt = torch.from_numpy(np.ascontiguousarray(w, dtype=np.float32)).cuda()
+    gs = torch.full((N,), np.nan, dtype=torch.complex64, device="cuda") if want[0] else None
+    gt = torch.full((K, M), np.nan, dtype=torch.complex64, device="cuda") if want[1] else None
+    ws = torch.empty(fd.fdas_backward_workspace_bytes(N, K, M, L, zchunk), dtype=torch.uint8,
+                     device="cuda")
+    fd._lib.fdas_correlate_backward_ex(spec, N, bank, K, M, L, wt, gs, gt, zchunk, ws)
+    torch.cuda.synchronize()
+    return (gs.cpu().numpy() if gs is not None else None,
+            gt.cpu().numpy() if gt is not None else None)
+
+
+def _rel(got, ref):
+    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("L", [256, 512, 1024, 2048, 4096, 8192])
+@pytest.mark.parametrize("case", ["ragged", "short", "B"])
+def test_grads_vs_oracle_random(fd, L, case):
+    M = min(64, L // 4)
+    B = L - M
+    N = {"ragged": 3 * B + 11, "short": 5, "B": B}[case]
+    K = 4
+    A = syn.random_spectrum(L + 7, N)
+    taps = syn.random_taps(L + 8, K, M)
+    w = np.random.default_rng(L).random((K, N), dtype=np.float32)
+    gA, gT = _grads(fd, A, taps, w, L)
+    rA, rT = native.grads(A, taps, w)
+    assert _rel(gA, rA) < TOL
+    assert _rel(gT, rT) < TOL
+
+
+def test_grads_partial_requests_and_zchunks(fd):
+    L, M, K, N = 1024, 128, 7, 5000
+    A = syn.random_spectrum(1, N)
+    taps = syn.random_taps(2, K, M)
+    w = np.random.default_rng(3).random((K, N), dtype=np.float32)
+    ref = _grads(fd, A, taps, w, L)
+    for zc in (1, 3, 7):
+        gA, gT = _grads(fd, A, taps, w, L, zchunk=zc)
+        assert _rel(gA, ref[0]) < 1e-6 and _rel(gT, ref[1]) < 1e-6
+    only_A = _grads(fd, A, taps, w, L, want=(True, False))
+    only_T = _grads(fd, A, taps, w, L, want=(False, True))
+    assert np.array_equal(only_A[0], ref[0]) and only_A[1] is None
+    assert np.array_equal(only_T[1], ref[1]) and only_T[0] is None
+    again = _grads(fd, A, taps, w, L)        # deterministic
+    assert np.array_equal(again[0], ref[0]) and np.array_equal(again[1], ref[1])
+
+
+def test_empty_spectrum_gives_zero_taps_gradient(fd):
+    taps = syn.random_taps(4, 3, 16)
+    gA, gT = _grads(fd, np.zeros(0, np.complex64), taps, np.zeros((3, 0), np.float32), 256)
+    assert gA.shape == (0,) and np.array_equal(gT, np.zeros((3, 16), np.complex64))
+
+
+def test_finite_differences_on_workload4_slice(fd):
+    # 4096-bin slice of the 2^20-bin workload, 9 templates z = -8..8, 128 taps
+    w4 = syn.workload(4)
+    A = w4.spectra[0][1 << 19:(1 << 19) + 4096].astype(np.complex128)
+    taps = ot.templates(8.0, 2.0, 128)
+    w = syn.loss_weights(4, 9, 4096)
+    gA, gT = _grads(fd, A, taps, w, 2048)
+    rA, rT = direct.grads(A, taps, w)
+    assert _rel(gA, rA) < TOL and _rel(gT, rT) < TOL
+    # FP64 central differences of the oracle loss along random directions
+    # (exact for this quadratic loss) against the GPU gradient
+    rng = np.random.default_rng(44)
+    L0 = lambda a, t: direct.loss(a, t, w)
+    for _ in range(3):
+        dA = rng.normal(size=A.shape) + 1j * rng.normal(size=A.shape)
+        h = 1e-2
+        fdA = (L0(A + h * dA, taps) - L0(A - h * dA, taps)) / (2 * h)
+        assert abs(np.real(np.vdot(gA, dA)) - fdA) < 1e-5 * abs(fdA) + 1e-5 * np.sum(np.abs(gA) * np.abs(dA))
+        dT = rng.normal(size=taps.shape) + 1j * rng.normal(size=taps.shape)
+        fdT = (L0(A, taps + h * dT) - L0(A, taps - h * dT)) / (2 * h)
+        assert abs(np.real(np.vdot(gT, dT)) - fdT) < 1e-5 * abs(fdT) + 1e-5 * np.sum(np.abs(gT) * np.abs(dT))
+
+
+def test_workload4_full(fd):
+    # 2^20 bins, 85 templates x 128 taps, segment 2048, w ~ U(0,1)
+    w4 = syn.workload(4)
+    A = w4.spectra[0]
+    K = w4.K
+    taps = fd.fdas_make_templates_host(w4.zmax, w4.dz, w4.M)
+    w = syn.loss_weights(4, K, len(A))
+    gA, gT = _grads(fd, A, taps, w, w4.L)
+    rA, rT = native.grads(A, taps, w)
+    assert _rel(gA, rA) < TOL
+    assert _rel(gT, rT) < TOL
+
+
+def test_autograd_function(fd):
+    from paper_1804_05335_amd.autograd import correlate
+    N, K, M, L = 3000, 5, 32, 256
+    A = syn.random_spectrum(9, N)
+    taps = syn.random_taps(10, K, M)
+    w = np.random.default_rng(11).random((K, N), dtype=np.float32)
+    spec = torch.from_numpy(A).cuda().requires_grad_(True)
+    tt = torch.from_numpy(taps).cuda().requires_grad_(True)
+    plane = correlate(spec, tt, L)
+    assert np.max(np.abs(plane.detach().cpu().numpy() - native.power(A, taps))) / \
+        native.power(A, taps).max() < TOL
+    (plane * torch.from_numpy(w).cuda()).sum().backward()
+    rA, rT = native.grads(A, taps, w)
+    assert _rel(spec.grad.cpu().numpy(), rA) < TOL
+    assert _rel(tt.grad.cpu().numpy(), rT) < TOL

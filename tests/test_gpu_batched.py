@@ -1,0 +1,152 @@
+"""GPU checks of the batched ragged correlation.
+
+The batched launch must give, for every spectrum, exactly (bitwise) the plane
+of a plain fdas_correlate call with the same segment length, and agree with
+the FP64 oracle to the benchmark spec's tolerance on sampled outputs -- also at the
+full 256-spectrum workload (ragged lengths in [2^18, 2^21] bins, 85 x 256
+taps) in the launch configuration the benchmark times.  A captured graph is
+replayed on new batches written in place.
+"""
+import numpy as np
+import pytest
+
+import fdas_synth as syn
+from oracle import native
+from oracle import templates as ot
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def fd():
+    import paper_1804_05335_amd as f
+    f.lib()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return f
+
+
+def _plain(fd, spec, bank, K, M, L):
+    return fd.correlate(spec, bank, K, M, L)
+
+
+def _views(planes, offs, K):
+    offs = offs.cpu().numpy()
+    return [planes[K * offs[b]:K * offs[b + 1]].view(K, int(offs[b + 1] - offs[b]))
+            for b in range(len(offs) - 1)]
+
+
+@pytest.mark.parametrize("L,zchunk,grid", [(2048, 0, 0), (2048, 7, 0), (1024, 0, 3),
+                                           (4096, 17, 64), (512, 0, 0)])
+def test_batched_bitwise_equals_plain(fd, L, zchunk, grid):
+    w = syn.workload(3, nspec=12, length_scale=1 / 64)
+    M = w.M if L >= 2 * w.M else L // 4
+    taps, bank = fd.make_bank(w.zmax, w.dz, M, L)
+    K = taps.shape[0]
+    spectra = [torch.from_numpy(s) for s in w.spectra]
+    # add degenerate members: empty, a single bin, exactly one segment
+    spectra.insert(3, torch.zeros(0, dtype=torch.complex64))
+    spectra.insert(5, torch.from_numpy(syn.random_spectrum(5, 1)))
+    spectra.append(torch.from_numpy(syn.random_spectrum(6, L - M)))
+    specs, offs = fd.pack(spectra)
+    planes = fd.correlate_batched(specs, offs, bank, K, M, L, zchunk=zchunk, grid=grid)
+    torch.cuda.synchronize()
+    for b, view in enumerate(_views(planes, offs, K)):
+        if view.shape[1] == 0:
+            continue
+        ref = _plain(fd, spectra[b].cuda(), bank, K, M, L)
+        assert torch.equal(view, ref), b
+
+
+def test_batched_vs_oracle_small(fd):
+    w = syn.workload(3, nspec=6, length_scale=1 / 128)
+    taps, bank = fd.make_bank(w.zmax, w.dz, w.M, 2048)
+    K = taps.shape[0]
+    specs, offs = fd.pack([torch.from_numpy(s) for s in w.spectra])
+    planes = fd.correlate_batched(specs, offs, bank, K, w.M, 2048)
+    T = ot.templates(w.zmax, w.dz, w.M)
+    for b, view in enumerate(_views(planes, offs, K)):
+        ref = native.power(w.spectra[b], T)
+        got = view.cpu().numpy()
+        assert np.max(np.abs(got - ref)) / np.max(ref) < TOL, b
+
+
+def test_graph_capture_and_replay_on_new_batches(fd):
+    # capture once, then rewrite offsets/spectra in place and replay; each
+    # replay must equal the eager result (several replays, eager work between)
+    L, M, zmax = 2048, 256, 20.0
+    taps, bank = fd.make_bank(zmax, 2.0, M, L)
+    K = taps.shape[0]
+    cap_bins = 300000
+    specs = torch.zeros(cap_bins, dtype=torch.complex64, device="cuda")
+    offs = torch.zeros(9, dtype=torch.int64, device="cuda")
+    planes = torch.zeros(K * cap_bins, dtype=torch.float32, device="cuda")
+    ws = torch.zeros(fd.fdas_batched_workspace_bytes(8), dtype=torch.uint8, device="cuda")
+
+    def fill(seed):
+        rng = np.random.default_rng(seed)
+        lens = rng.integers(0, 37000, 8)
+        o = np.zeros(9, dtype=np.int64)
+        o[1:] = np.cumsum(lens)
+        data = syn.random_spectrum(seed, int(o[-1]))
+        specs[:o[-1]].copy_(torch.from_numpy(data))
+        offs.copy_(torch.from_numpy(o))
+        return o
+
+    fill(1)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):   # warm-up outside capture
+        fd.correlate_batched(specs, offs, bank, K, M, L, planes=planes, ws=ws)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fd.correlate_batched(specs, offs, bank, K, M, L, planes=planes, ws=ws)
+    for seed in (2, 3, 4, 5):
+        o = fill(seed)
+        planes.fill_(-1.0)
+        g.replay()
+        torch.cuda.synchronize()
+        got = planes[:K * o[-1]].clone()
+        eager = fd.correlate_batched(specs, offs, bank, K, M, L)
+        torch.cuda.synchronize()
+        assert torch.equal(got, eager[:K * o[-1]]), seed
+        _ = torch.randn(1000, device="cuda").sum()   # unrelated eager work between replays
+
+
+def test_workload3_full_sampled(fd):
+    # 256 ragged spectra, 85 templates x 256 taps, segment 2048 (the
+    # benchmark's launch configuration); plane ~ 78 GB in HBM
+    w = syn.workload(3)
+    L = w.L
+    taps, bank = fd.make_bank(w.zmax, w.dz, w.M, L)
+    K = taps.shape[0]
+    packed, o = w.packed()
+    specs = torch.from_numpy(packed).cuda()
+    offs = torch.from_numpy(o).cuda()
+    planes = fd.correlate_batched(specs, offs, bank, K, w.M, L)
+    torch.cuda.synchronize()
+    T = ot.templates(w.zmax, w.dz, w.M)
+    rng = np.random.default_rng(3)
+    views = _views(planes, offs, K)
+    for b in rng.choice(len(w.spectra), size=8, replace=False):
+        n = len(w.spectra[b])
+        B = L - w.M
+        cols = np.unique(np.concatenate([
+            np.arange(0, 64), np.arange(n - 64, n), rng.integers(0, n, 3000),
+            (np.arange(1, -(-n // B)) * B)[:, None] + np.arange(-2, 3)[None, :]]).ravel())
+        cols = cols[(cols >= 0) & (cols < n)]
+        zi = np.repeat(np.arange(K), len(cols)).astype(np.int32)
+        ri = np.tile(cols, K).astype(np.int64)
+        got = views[b][torch.from_numpy(zi.astype(np.int64)).cuda(),
+                       torch.from_numpy(ri).cuda()].cpu().numpy()
+        ref = native.power_points(w.spectra[b], T, zi, ri)
+        assert np.max(np.abs(got - ref)) / np.max(ref) < TOL, b
+        # and bitwise equal to the plain path on this spectrum
+        ref_plain = _plain(fd, specs[o[b]:o[b + 1]], bank, K, w.M, L)
+        assert torch.equal(views[b], ref_plain), b
+    assert bool(torch.isfinite(planes).all())
