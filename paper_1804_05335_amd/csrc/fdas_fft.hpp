@@ -74,20 +74,61 @@ __device__ __forceinline__ float2 rot8_3(float2 a)
 }
 
 // ---- radix-R DFT codelets, natural order in and out ----------------------
+//
+// Every codelet starts with radix-2 butterflies pairing element i with
+// i + R/2.  That first stage is split out so a per-element multiplier (a
+// twiddle, or the template H) can be fused into it with FMAs:
+//   a = x_i w_i,  s = a + x_{i+R/2} w_{i+R/2} (4 FMA),  d = 2a - s (2 FMA),
+// 10 instructions per pair instead of 12 (6 instead of 8 when w_i = 1).
 
-template <bool INV>
-__device__ __forceinline__ void dft2(float2 (&x)[2])
+enum MulMode { kNoMul = 0, kMul = 1, kMulConj = 2 };
+
+template <int MODE>
+__device__ __forceinline__ float2 mulw(float2 x, float2 w)
 {
-    float2 a = x[0], b = x[1];
-    x[0] = cadd(a, b);
-    x[1] = csub(a, b);
+    if constexpr (MODE == kMul) return cmul(x, w);
+    else if constexpr (MODE == kMulConj) return cmulc(x, w);
+    else return x;
 }
 
-template <bool INV>
-__device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2& x3)
+// a + x*w (or a + x*conj(w)) in 4 FMAs
+template <int MODE>
+__device__ __forceinline__ float2 add_mulw(float2 a, float2 x, float2 w)
 {
-    float2 t0 = cadd(x0, x2), t1 = csub(x0, x2);
-    float2 t2 = cadd(x1, x3), t3 = rot4<INV>(csub(x1, x3));
+    if constexpr (MODE == kMul)
+        return make_float2(fmaf(x.x, w.x, fmaf(-x.y, w.y, a.x)), fmaf(x.x, w.y, fmaf(x.y, w.x, a.y)));
+    else if constexpr (MODE == kMulConj)
+        return make_float2(fmaf(x.x, w.x, fmaf(x.y, w.y, a.x)), fmaf(x.y, w.x, fmaf(-x.x, w.y, a.y)));
+    else
+        return cadd(a, x);
+}
+
+// First stage: x[i], x[i+R/2] <- a + b, a - b with a = x[i] w[i], b = x[i+R/2] w[i+R/2].
+// FIRST_ONE: w[0] is 1 (not read).
+template <int R, int MODE, bool FIRST_ONE>
+__device__ __forceinline__ void stage1(float2 (&x)[R], const float2 (&w)[R])
+{
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) {
+        if constexpr (MODE == kNoMul) {
+            const float2 a = x[i], b = x[i + R / 2];
+            x[i] = cadd(a, b);
+            x[i + R / 2] = csub(a, b);
+        } else {
+            const float2 a = (FIRST_ONE && i == 0) ? x[i] : mulw<MODE>(x[i], w[i]);
+            const float2 sum = add_mulw<MODE>(a, x[i + R / 2], w[i + R / 2]);
+            x[i] = sum;
+            x[i + R / 2] = make_float2(fmaf(2.f, a.x, -sum.x), fmaf(2.f, a.y, -sum.y));
+        }
+    }
+}
+
+// Remaining stages, given stage1 has run.
+template <bool INV>
+__device__ __forceinline__ void rest4(float2& x0, float2& x1, float2& x2, float2& x3)
+{
+    // after stage 1: x0 = t0, x2 = t1, x1 = t2, x3 = t3' (pairs (0,2), (1,3))
+    const float2 t0 = x0, t1 = x2, t2 = x1, t3 = rot4<INV>(x3);
     x0 = cadd(t0, t2);
     x2 = csub(t0, t2);
     x1 = cadd(t1, t3);
@@ -95,70 +136,78 @@ __device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2&
 }
 
 template <bool INV>
-__device__ __forceinline__ void dft4(float2 (&x)[4])
+__device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2& x3)
 {
-    dft4<INV>(x[0], x[1], x[2], x[3]);
-}
-
-template <bool INV>
-__device__ __forceinline__ void dft8(float2 (&x)[8])
-{
-    float2 e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
-    float2 o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
-    dft4<INV>(e0, e1, e2, e3);
-    dft4<INV>(o0, o1, o2, o3);
-    o1 = rot8_1<INV>(o1);
-    o2 = rot4<INV>(o2);
-    o3 = rot8_3<INV>(o3);
-    x[0] = cadd(e0, o0); x[4] = csub(e0, o0);
-    x[1] = cadd(e1, o1); x[5] = csub(e1, o1);
-    x[2] = cadd(e2, o2); x[6] = csub(e2, o2);
-    x[3] = cadd(e3, o3); x[7] = csub(e3, o3);
-}
-
-// 16 = 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2.
-template <bool INV>
-__device__ __forceinline__ void dft16(float2 (&x)[16])
-{
-#pragma unroll
-    for (int n2 = 0; n2 < 4; ++n2)
-        dft4<INV>(x[n2], x[4 + n2], x[8 + n2], x[12 + n2]);
-    // now x[4 k1 + n2] holds Y[n2][k1]; twiddle by W16^(n2 k1)
-    const float2 w1 = make_float2(kCos8, INV ? kSin8 : -kSin8);
-    const float2 w3 = make_float2(kSin8, INV ? kCos8 : -kCos8);
-    const float2 w9 = make_float2(-kCos8, INV ? -kSin8 : kSin8);
-    x[4 + 1] = twiddle<false>(x[4 + 1], w1);      // n2=1,k1=1: W^1
-    x[4 + 2] = rot8_1<INV>(x[4 + 2]);             // n2=2,k1=1: W^2
-    x[4 + 3] = twiddle<false>(x[4 + 3], w3);      // n2=3,k1=1: W^3
-    x[8 + 1] = rot8_1<INV>(x[8 + 1]);             // n2=1,k1=2: W^2
-    x[8 + 2] = rot4<INV>(x[8 + 2]);               // n2=2,k1=2: W^4
-    x[8 + 3] = rot8_3<INV>(x[8 + 3]);             // n2=3,k1=2: W^6
-    x[12 + 1] = twiddle<false>(x[12 + 1], w3);    // n2=1,k1=3: W^3
-    x[12 + 2] = rot8_3<INV>(x[12 + 2]);           // n2=2,k1=3: W^6
-    x[12 + 3] = twiddle<false>(x[12 + 3], w9);    // n2=3,k1=3: W^9
-#pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1)
-        dft4<INV>(x[4 * k1 + 0], x[4 * k1 + 1], x[4 * k1 + 2], x[4 * k1 + 3]);
-    // x[4 k1 + k2] holds X[k1 + 4 k2]; transpose the 4x4 index back
-    float2 y[16];
-#pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1)
-#pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2)
-            y[k1 + 4 * k2] = x[4 * k1 + k2];
-#pragma unroll
-    for (int i = 0; i < 16; ++i)
-        x[i] = y[i];
+    float2 a = x0, b = x2, c = x1, d = x3;
+    x0 = cadd(a, b); x2 = csub(a, b);
+    x1 = cadd(c, d); x3 = csub(c, d);
+    rest4<INV>(x0, x1, x2, x3);
 }
 
 template <int R, bool INV>
-__device__ __forceinline__ void dft(float2 (&x)[R])
+__device__ __forceinline__ void rest(float2 (&x)[R])
 {
-    if constexpr (R == 2) dft2<INV>(x);
-    else if constexpr (R == 4) dft4<INV>(x);
-    else if constexpr (R == 8) dft8<INV>(x);
-    else if constexpr (R == 16) dft16<INV>(x);
-    else static_assert(R == 2 || R == 4 || R == 8 || R == 16, "unsupported radix");
+    if constexpr (R == 2) {
+        // nothing after the single butterfly
+    } else if constexpr (R == 4) {
+        rest4<INV>(x[0], x[1], x[2], x[3]);
+    } else if constexpr (R == 8) {
+        // evens e = (x0, x2, x4, x6), odds o = (x1, x3, x5, x7); stage 1 paired
+        // (0,4), (2,6), (1,5), (3,7), i.e. the first stage of both radix-4 DFTs
+        float2 e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
+        float2 o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
+        rest4<INV>(e0, e1, e2, e3);
+        rest4<INV>(o0, o1, o2, o3);
+        o1 = rot8_1<INV>(o1);
+        o2 = rot4<INV>(o2);
+        o3 = rot8_3<INV>(o3);
+        x[0] = cadd(e0, o0); x[4] = csub(e0, o0);
+        x[1] = cadd(e1, o1); x[5] = csub(e1, o1);
+        x[2] = cadd(e2, o2); x[6] = csub(e2, o2);
+        x[3] = cadd(e3, o3); x[7] = csub(e3, o3);
+    } else if constexpr (R == 16) {
+        // 16 = 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2.  Stage 1 paired (n2, 8+n2)
+        // and (4+n2, 12+n2): the first stage of each radix-4 DFT over n1.
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2)
+            rest4<INV>(x[n2], x[4 + n2], x[8 + n2], x[12 + n2]);
+        // x[4 k1 + n2] holds Y[n2][k1]; twiddle by W16^(n2 k1)
+        const float2 w1 = make_float2(kCos8, INV ? kSin8 : -kSin8);
+        const float2 w3 = make_float2(kSin8, INV ? kCos8 : -kCos8);
+        const float2 w9 = make_float2(-kCos8, INV ? -kSin8 : kSin8);
+        x[4 + 1] = cmul(x[4 + 1], w1);
+        x[4 + 2] = rot8_1<INV>(x[4 + 2]);
+        x[4 + 3] = cmul(x[4 + 3], w3);
+        x[8 + 1] = rot8_1<INV>(x[8 + 1]);
+        x[8 + 2] = rot4<INV>(x[8 + 2]);
+        x[8 + 3] = rot8_3<INV>(x[8 + 3]);
+        x[12 + 1] = cmul(x[12 + 1], w3);
+        x[12 + 2] = rot8_3<INV>(x[12 + 2]);
+        x[12 + 3] = cmul(x[12 + 3], w9);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1)
+            dft4<INV>(x[4 * k1 + 0], x[4 * k1 + 1], x[4 * k1 + 2], x[4 * k1 + 3]);
+        // x[4 k1 + k2] holds X[k1 + 4 k2]; transpose the 4x4 index back
+        float2 y[16];
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2)
+                y[k1 + 4 * k2] = x[4 * k1 + k2];
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            x[i] = y[i];
+    } else {
+        static_assert(R == 2 || R == 4 || R == 8 || R == 16, "unsupported radix");
+    }
+}
+
+// DFT_R of x[i] * w[i] (MODE selects the multiplier; FIRST_ONE: w[0] = 1).
+template <int R, bool INV, int MODE, bool FIRST_ONE>
+__device__ __forceinline__ void dft_mul(float2 (&x)[R], const float2 (&w)[R])
+{
+    stage1<R, MODE, FIRST_ONE>(x, w);
+    rest<R, INV>(x);
 }
 
 // ---- transform plans ---------------------------------------------------------
@@ -206,11 +255,16 @@ __device__ __forceinline__ void load_twiddles(float2 (&tw)[NTW], const float2* _
         load_twiddles<L, E, NS * R, OFF + (NS > 1 ? NB * (R - 1) : 0), NTW, Rest...>(tw, table, t);
 }
 
-// Run the passes from NS on.  v holds positions t + T*m; on return v holds
-// the transform at the same positions.  Exchanges ping-pong between the two
-// LDS buffers (one barrier per exchange).
-template <int L, int E, bool INV, int NS, int OFF, int NTW, int R, int... Rest>
-__device__ __forceinline__ void run_passes(float2 (&v)[E], float2*& lds_a, float2*& lds_b,
+// Run the passes from NS on.  The first of them reads `in` (positions
+// t + T*m of this lane), the rest read v; on return v holds the transform at
+// the same positions (in and v may be the same array; `in` is not written
+// unless it is v).  The first pass (NS = 1) may fuse a per-element
+// multiplier pre[m] (MODE0: kMul or kMulConj) into its first butterfly
+// stage; later passes fuse their twiddles the same way.  Exchanges
+// ping-pong between the two LDS buffers (one barrier each).
+template <int L, int E, bool INV, int MODE0, int NS, int OFF, int NTW, int R, int... Rest>
+__device__ __forceinline__ void run_passes(const float2 (&in)[E], const float2 (&pre)[E],
+                                           float2 (&v)[E], float2*& lds_a, float2*& lds_b,
                                            const float2 (&tw)[NTW], int t)
 {
     constexpr int T = L / E, NB = E / R;
@@ -220,13 +274,24 @@ __device__ __forceinline__ void run_passes(float2 (&v)[E], float2*& lds_a, float
         float2 x[R];
 #pragma unroll
         for (int i = 0; i < R; ++i)
-            x[i] = v[u + i * NB];
+            x[i] = in[u + i * NB];
         if constexpr (NS > 1) {
+            float2 w[R];
+            w[0] = make_float2(1.f, 0.f);
 #pragma unroll
             for (int i = 1; i < R; ++i)
-                x[i] = twiddle<INV>(x[i], tw[OFF + u * (R - 1) + (i - 1)]);
+                w[i] = tw[OFF + u * (R - 1) + (i - 1)];
+            dft_mul<R, INV, INV ? kMulConj : kMul, true>(x, w);
+        } else if constexpr (MODE0 != kNoMul) {
+            float2 w[R];
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+                w[i] = pre[u + i * NB];
+            dft_mul<R, INV, MODE0, false>(x, w);
+        } else {
+            float2 w[R];
+            dft_mul<R, INV, kNoMul, false>(x, w);
         }
-        dft<R, INV>(x);
         if constexpr (LAST) {
 #pragma unroll
             for (int i = 0; i < R; ++i)
@@ -247,7 +312,8 @@ __device__ __forceinline__ void run_passes(float2 (&v)[E], float2*& lds_a, float
         float2* tmp = lds_a;
         lds_a = lds_b;
         lds_b = tmp;
-        run_passes<L, E, INV, NS * R, OFF + (NS > 1 ? NB * (R - 1) : 0), NTW, Rest...>(v, lds_a, lds_b, tw, t);
+        run_passes<L, E, INV, kNoMul, NS * R, OFF + (NS > 1 ? NB * (R - 1) : 0), NTW, Rest...>(
+            v, pre, v, lds_a, lds_b, tw, t);
     }
 }
 
@@ -266,11 +332,19 @@ struct FFT<L, E, Radices<Rs...>> {
     {
         load_twiddles<L, E, 1, 0, NTW, Rs...>(tw, table, t);
     }
+    // transform of v (forward: INV = false)
     template <bool INV>
     __device__ static void run(float2 (&v)[E], float2*& lds_a, float2*& lds_b,
                                const float2 (&tw)[NTW], int t)
     {
-        run_passes<L, E, INV, 1, 0, NTW, Rs...>(v, lds_a, lds_b, tw, t);
+        run_passes<L, E, INV, kNoMul, 1, 0, NTW, Rs...>(v, v, v, lds_a, lds_b, tw, t);
+    }
+    // v = transform of in[m] * pre[m] (MODE kMul) or in[m] * conj(pre[m]) (kMulConj)
+    template <bool INV, int MODE>
+    __device__ static void run_mul(const float2 (&in)[E], const float2 (&pre)[E], float2 (&v)[E],
+                                   float2*& lds_a, float2*& lds_b, const float2 (&tw)[NTW], int t)
+    {
+        run_passes<L, E, INV, MODE, 1, 0, NTW, Rs...>(in, pre, v, lds_a, lds_b, tw, t);
     }
 };
 

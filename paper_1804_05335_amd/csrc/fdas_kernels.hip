@@ -85,8 +85,37 @@ struct Fwd {
     static constexpr int T = F::T;
     static constexpr int NTW = F::NTW;
 
+    __device__ static void load_row(float2 (&H)[E], const float2* __restrict__ bank, int row, int t)
+    {
+        const float2* h = bank + (int64_t)row * L + t;
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            H[m] = h[T * m];
+    }
+
+    // inverse transform of X * H_z, then |.|^2 of the valid outputs to row z
+    __device__ static void one_template(const float2 (&X)[E], const float2 (&H)[E], int64_t N,
+                                        int M, int64_t out0, int z, float* __restrict__ plane,
+                                        const float2 (&tw)[NTW], float2*& la, float2*& lb, int t)
+    {
+        const int B = L - M;
+        float2 v[E];
+        F::template run_mul<true, kMul>(X, H, v, la, lb, tw, t);
+        float* row = plane + (int64_t)z * N + out0;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int u = t + T * m - M / 2;
+            if (u >= 0 && u < B && out0 + u < N) {
+                const float p = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
+                __builtin_nontemporal_store(p, row + (unsigned)u);
+            }
+        }
+    }
+
+    // K: rows in the bank before the twiddle row (row K is always readable,
+    // so the H prefetch of the next template is unconditional)
     __device__ static void item(const float2* __restrict__ spec, int64_t N,
-                                const float2* __restrict__ bank, int M, int64_t s, int z0,
+                                const float2* __restrict__ bank, int K, int M, int64_t s, int z0,
                                 int z1, float* __restrict__ plane, const float2 (&tw)[NTW],
                                 float2*& la, float2*& lb, int t)
     {
@@ -102,34 +131,16 @@ struct Fwd {
         }
         F::template run<false>(X, la, lb, tw, t);
 
-        float2 H[E];
-        {
-            const float2* hz = bank + (int64_t)z0 * L + t;
-#pragma unroll
-            for (int m = 0; m < E; ++m)
-                H[m] = hz[T * m];
-        }
-        for (int z = z0; z < z1; ++z) {
-            float2 v[E];
-#pragma unroll
-            for (int m = 0; m < E; ++m)
-                v[m] = cmul(X[m], H[m]);
-            if (z + 1 < z1) {
-                const float2* hz = bank + (int64_t)(z + 1) * L + t;
-#pragma unroll
-                for (int m = 0; m < E; ++m)
-                    H[m] = hz[T * m];
-            }
-            F::template run<true>(v, la, lb, tw, t);
-            float* row = plane + (int64_t)z * N + out0;
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int u = t + T * m - M / 2;
-                if (u >= 0 && u < B && out0 + u < N) {
-                    const float p = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
-                    __builtin_nontemporal_store(p, row + u);
-                }
-            }
+        // two H buffers, two templates per trip: the prefetch of the next
+        // template's row never needs a register copy
+        float2 Ha[E], Hb[E];
+        load_row(Ha, bank, z0, t);
+        for (int z = z0; z < z1; z += 2) {
+            load_row(Hb, bank, min(z + 1, K), t);
+            one_template(X, Ha, N, M, out0, z, plane, tw, la, lb, t);
+            load_row(Ha, bank, min(z + 2, K), t);
+            if (z + 1 < z1)
+                one_template(X, Hb, N, M, out0, z + 1, plane, tw, la, lb, t);
         }
     }
 };
@@ -149,7 +160,7 @@ __global__ __launch_bounds__(Fwd<L>::T) void forward_kernel(
     float2* lb = lds[1];
     const int z0 = blockIdx.y * zchunk;
     const int z1 = min(K, z0 + zchunk);
-    W::item(spec, N, bank, M, blockIdx.x, z0, z1, plane, tw, la, lb, t);
+    W::item(spec, N, bank, K, M, blockIdx.x, z0, z1, plane, tw, la, lb, t);
 }
 
 // ---- adjoint (backward) ------------------------------------------------------
@@ -199,12 +210,10 @@ struct Bwd {
             acc[m] = make_float2(0.f, 0.f);
 
         for (int z = z0; z < z1; ++z) {
-            const float2* hz = bank + (int64_t)z * L + t;
+            float2 H[E];
+            W::load_row(H, bank, z, t);
             float2 v[E];
-#pragma unroll
-            for (int m = 0; m < E; ++m)
-                v[m] = cmul(X[m], hz[T * m]);
-            F::template run<true>(v, la, lb, tw, t);
+            F::template run_mul<true, kMul>(X, H, v, la, lb, tw, t);     // y = IFFT(X H_z)
             // g = 2 w y on the owned outputs, zero elsewhere
             const float* wz = dLdP + (int64_t)z * N + out0;
 #pragma unroll
@@ -212,22 +221,19 @@ struct Bwd {
                 const int u = t + T * m - M / 2;
                 float wv = 0.f;
                 if (u >= 0 && u < B && out0 + u < N)
-                    wv = 2.f * wz[u];
+                    wv = 2.f * wz[(unsigned)u];
                 v[m] = make_float2(wv * v[m].x, wv * v[m].y);
             }
-            F::template run<false>(v, la, lb, tw, t);
+            F::template run<false>(v, la, lb, tw, t);                     // G = FFT(g)
             if (want_A) {
 #pragma unroll
-                for (int m = 0; m < E; ++m) {
-                    const float2 c = cmulc(v[m], hz[T * m]);
-                    acc[m] = cadd(acc[m], c);
+                for (int m = 0; m < E; ++m) {                             // acc += conj(H) G
+                    acc[m].x = fmaf(v[m].x, H[m].x, fmaf(v[m].y, H[m].y, acc[m].x));
+                    acc[m].y = fmaf(v[m].y, H[m].x, fmaf(-v[m].x, H[m].y, acc[m].y));
                 }
             }
             if (want_T) {
-#pragma unroll
-                for (int m = 0; m < E; ++m)
-                    v[m] = cmulc(X[m], v[m]);          // X conj(G)
-                F::template run<true>(v, la, lb, tw, t);
+                F::template run_mul<true, kMulConj>(X, v, v, la, lb, tw, t);  // IFFT(X conj(G))
                 float2* pz = partT + (int64_t)z * M;
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
@@ -389,7 +395,7 @@ __global__ __launch_bounds__(Fwd<L>::T) void batched_kernel(
         const int64_t Nb = offsets[b + 1] - off;
         const int z0 = zc * zchunk;
         const int z1 = min(K, z0 + zchunk);
-        W::item(specs + off, Nb, bank, M, tile - segpre[b], z0, z1, planes + (int64_t)K * off,
+        W::item(specs + off, Nb, bank, K, M, tile - segpre[b], z0, z1, planes + (int64_t)K * off,
                 tw, la, lb, t);
     }
 }

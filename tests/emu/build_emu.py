@@ -1,0 +1,25 @@
+"""Build the CPU emulation of libfdas (test infrastructure only): the same
+C-ABI and kernel sources compiled with g++ against tests/emu/hip/*.h, where
+each workgroup runs as threads on the host.  Output: tests/emu/_build/libfdas_emu.so."""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+CSRC = os.path.join(ROOT, "paper_1804_05335_amd", "csrc")
+OUT = os.path.join(HERE, "_build", "libfdas_emu.so")
+
+
+def build() -> str:
+    os.makedirs(os.path.dirname(OUT), exist_ok=True)
+    srcs = [os.path.join(CSRC, f) for f in ("fdas_api.cpp", "fdas_templates.cpp", "fdas_kernels.hip")]
+    tmp = OUT + f".tmp{os.getpid()}"
+    cmd = ["g++", "-O2", "-std=c++20", "-fPIC", "-shared", "-pthread", "-I", HERE,
+           "-I", os.path.join(ROOT, "include"), "-x", "c++"] + srcs + ["-o", tmp]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, OUT)
+    return OUT
+
+
+if __name__ == "__main__":
+    print(build())

@@ -1,0 +1,82 @@
+// CPU emulation of the small part of the HIP runtime and device language the
+// FDAS kernels use (test infrastructure only).  Every workgroup runs as
+// blockDim.x std::threads sharing `static` (= __shared__) arrays, with a
+// std::barrier standing for __syncthreads; blocks run one after another.
+// Device pointers are plain host pointers.  Used to check the kernels'
+// indexing, masking and data flow on machines without a GPU.
+#pragma once
+#include <algorithm>
+#include <atomic>
+#include <barrier>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#define __device__
+#define __host__
+#define __global__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __shared__ static
+#define __restrict__
+#define __builtin_nontemporal_store(v, p) (*(p) = (v))
+
+struct float2 { float x, y; };
+inline float2 make_float2(float a, float b) { return float2{a, b}; }
+struct dim3 {
+    unsigned x, y, z;
+    dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+struct EmuIdx { unsigned x = 0, y = 0, z = 0; };
+inline thread_local EmuIdx threadIdx;
+inline EmuIdx blockIdx, gridDim, blockDim;
+inline std::barrier<>* emu_barrier = nullptr;
+inline void __syncthreads() { emu_barrier->arrive_and_wait(); }
+
+using std::max;
+using std::min;
+inline void sincospi(double x, double* s, double* c) { *s = std::sin(M_PI * x); *c = std::cos(M_PI * x); }
+
+typedef int hipError_t;
+enum { hipSuccess = 0, hipErrorInvalidValue = 1 };
+enum hipMemcpyKind { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2 };
+typedef struct ihipStream_t* hipStream_t;
+enum { hipDeviceAttributeMultiprocessorCount = 0 };
+inline hipError_t hipGetLastError() { return hipSuccess; }
+inline const char* hipGetErrorString(hipError_t) { return "emulated"; }
+inline hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
+inline hipError_t hipDeviceGetAttribute(int* v, int, int) { *v = 3; return hipSuccess; }
+template <class F>
+hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, F, int, int) { *n = 1; return hipSuccess; }
+inline hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t)
+{
+    std::memcpy(d, s, n);
+    return hipSuccess;
+}
+inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+
+template <class K, class... A>
+void emu_launch(K kernel, dim3 grid, dim3 block, A... args)
+{
+    gridDim = EmuIdx{grid.x, grid.y, grid.z};
+    blockDim = EmuIdx{block.x, block.y, block.z};
+    for (unsigned bz = 0; bz < grid.z; ++bz)
+        for (unsigned by = 0; by < grid.y; ++by)
+            for (unsigned bx = 0; bx < grid.x; ++bx) {
+                blockIdx = EmuIdx{bx, by, bz};
+                std::barrier<> bar(block.x);
+                emu_barrier = &bar;
+                std::vector<std::thread> th;
+                th.reserve(block.x);
+                for (unsigned t = 0; t < block.x; ++t)
+                    th.emplace_back([=]() {
+                        threadIdx = EmuIdx{t, 0, 0};
+                        kernel(args...);
+                    });
+                for (auto& x : th)
+                    x.join();
+            }
+}
+#define hipLaunchKernelGGL(k, grid, block, shmem, stream, ...) emu_launch(k, dim3(grid), dim3(block), __VA_ARGS__)

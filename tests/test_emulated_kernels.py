@@ -1,0 +1,123 @@
+"""The HIP kernel sources, compiled for the CPU emulation in tests/emu (each
+workgroup runs as host threads with a barrier for __syncthreads), driven
+through the same C ABI with host arrays and checked against the FP64 oracle.
+
+This checks the kernels' indexing, masking, batching and adjoint data flow
+where no GPU is present.  It says nothing about GPU execution; the GPU parity
+tests (tests/test_gpu_*.py) do that.
+"""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import fdas_synth as syn
+from oracle import native
+from oracle import templates as ot
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def emu():
+    from tests.emu import build_emu
+    path = build_emu.build()
+    L = ctypes.CDLL(path)
+    return L
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _bank(emu, taps, L):
+    K, M = taps.shape
+    taps = np.ascontiguousarray(taps, dtype=np.complex64)
+    bank = np.zeros((K + 1) * L, dtype=np.complex64)
+    assert emu.fdas_prepare_bank(_p(taps), K, M, L, _p(bank), None) == 0
+    return bank
+
+
+def _rel(got, ref):
+    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("L,M,N,zchunk", [(256, 32, 1000, 0), (512, 64, 449, 2), (2048, 256, 3900, 0),
+                                          (256, 128, 300, 1), (1024, 2, 2000, 3)])
+def test_emulated_forward_vs_oracle(emu, L, M, N, zchunk):
+    K = 3
+    A = syn.random_spectrum(L + N, N)
+    taps = syn.random_taps(M + K, K, M)
+    bank = _bank(emu, taps, L)
+    plane = np.full((K, N), np.nan, dtype=np.float32)
+    assert emu.fdas_correlate_ex(_p(A), ctypes.c_int64(N), _p(bank), K, M, L, _p(plane),
+                                 zchunk, None) == 0
+    assert _rel(plane, native.power(A, taps)) < TOL
+
+
+def test_emulated_templates_forward_workload1_slice(emu):
+    # the library's own templates and bank on a 4000-bin slice of workload 1
+    w = syn.workload(1)
+    A = np.ascontiguousarray(w.spectra[0][18000:22000])
+    K, M, L = w.K, w.M, w.L
+    taps = np.zeros((K, M), dtype=np.complex64)
+    bank = np.zeros((K + 1) * L, dtype=np.complex64)
+    assert emu.fdas_make_templates(ctypes.c_double(w.zmax), ctypes.c_double(w.dz), M, L,
+                                   _p(taps), _p(bank), None) == 0
+    plane = np.zeros((K, len(A)), dtype=np.float32)
+    assert emu.fdas_correlate(_p(A), ctypes.c_int64(len(A)), _p(bank), K, M, L, _p(plane), None) == 0
+    ref = native.power(A, ot.templates(w.zmax, w.dz, M))
+    assert _rel(plane, ref) < TOL
+    zz, rr = np.unravel_index(np.argmax(plane), plane.shape)
+    assert (zz, rr) == (14, 2000)        # z = +8, r = 20000 - 18000
+
+
+def test_emulated_batched_equals_plain(emu):
+    L, M, K = 512, 64, 3
+    lens = [700, 0, 1, 448, 1203, 5]
+    taps = syn.random_taps(7, K, M)
+    bank = _bank(emu, taps, L)
+    specs = [syn.random_spectrum(10 + i, n) for i, n in enumerate(lens)]
+    packed = np.concatenate(specs).astype(np.complex64)
+    offs = np.zeros(len(lens) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(lens)
+    planes = np.full(K * offs[-1], np.nan, dtype=np.float32)
+    emu.fdas_batched_workspace_bytes.restype = ctypes.c_size_t
+    wsb = emu.fdas_batched_workspace_bytes(len(lens))
+    ws = np.zeros(wsb, dtype=np.uint8)
+    for zc, grid in [(0, 0), (2, 5)]:
+        planes[:] = np.nan
+        assert emu.fdas_correlate_batched_ex(_p(packed), _p(offs), len(lens), _p(bank), K, M, L,
+                                             _p(planes), zc, grid, _p(ws), ctypes.c_size_t(wsb),
+                                             None) == 0
+        for b, n in enumerate(lens):
+            if n == 0:
+                continue
+            view = planes[K * offs[b]:K * offs[b + 1]].reshape(K, n)
+            one = np.zeros((K, n), dtype=np.float32)
+            assert emu.fdas_correlate(_p(specs[b]), ctypes.c_int64(n), _p(bank), K, M, L,
+                                      _p(one), None) == 0
+            assert np.array_equal(view, one), b
+            assert _rel(view, native.power(specs[b], taps)) < TOL
+
+
+@pytest.mark.parametrize("L,M,N", [(256, 32, 900), (512, 128, 600), (2048, 256, 2500)])
+def test_emulated_backward_vs_oracle(emu, L, M, N):
+    K = 3
+    A = syn.random_spectrum(3 * L, N)
+    taps = syn.random_taps(5 * M, K, M)
+    w = np.random.default_rng(N).random((K, N), dtype=np.float32)
+    bank = _bank(emu, taps, L)
+    emu.fdas_backward_workspace_bytes.restype = ctypes.c_size_t
+    wsb = emu.fdas_backward_workspace_bytes(ctypes.c_int64(N), K, M, L, 0)
+    ws = np.zeros(wsb + 256, dtype=np.uint8)
+    wsp = ctypes.c_void_p((ws.ctypes.data + 255) & ~255)
+    gA = np.full(N, np.nan, dtype=np.complex64)
+    gT = np.full((K, M), np.nan, dtype=np.complex64)
+    assert emu.fdas_correlate_backward(_p(A), ctypes.c_int64(N), _p(bank), K, M, L, _p(w),
+                                       _p(gA), _p(gT), wsp, ctypes.c_size_t(wsb), None) == 0
+    rA, rT = native.grads(A, taps, w)
+    assert _rel(gA, rA) < TOL
+    assert _rel(gT, rT) < TOL
