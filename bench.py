@@ -74,16 +74,16 @@ def read_traffic(name: str):
         return None
 
 
-def time_forward(fdas, torch, spec, N, bank, K, M, L, plane, steps, warmup, zchunk=0):
+def time_forward(fdas, torch, spec, N, bank, K, M, L, plane, steps, warmup, grid=0):
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
-        fdas.fdas_correlate_ex(spec, N, bank, K, M, L, plane, zchunk)
+        fdas.fdas_correlate_ex(spec, N, bank, K, M, L, plane, grid)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record(stream)
     for _ in range(steps):
-        fdas.fdas_correlate_ex(spec, N, bank, K, M, L, plane, zchunk)
+        fdas.fdas_correlate_ex(spec, N, bank, K, M, L, plane, grid)
     t1.record(stream)
     torch.cuda.synchronize()
     return t0.elapsed_time(t1) / steps      # ms per launch (one launch per step)
@@ -109,15 +109,131 @@ def cpu_baseline(spec_np, zmax, dz, M, K, target_s: float):
                       f"2^21-bin spectrum, direct FP64 sum over {M} taps"}
 
 
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _timed(torch, fn, steps):
+    """Mean ms per call of fn() over `steps` calls on the current stream."""
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    a, b = _events(torch)
+    a.record(stream)
+    for _ in range(steps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def bench_batched(fdas, torch, steps: int):
+    """256 ragged spectra (2^18..2^21 bins), 85 x 256 taps: one persistent
+    launch, the same launch replayed from a captured graph, and a loop of
+    plain per-spectrum calls over the same data and plane layout."""
+    import fdas_synth as syn
+    w = syn.workload(3)
+    packed, o = w.packed()
+    K, M, L = w.K, w.M, w.L
+    specs = torch.from_numpy(packed).cuda()
+    offs = torch.from_numpy(o).cuda()
+    del packed
+    _, bank = fdas.make_bank(w.zmax, w.dz, M, L)
+    planes = torch.empty(K * int(o[-1]), dtype=torch.float32, device="cuda")
+    ws = torch.empty(fdas.fdas_batched_workspace_bytes(len(w.spectra)), dtype=torch.uint8,
+                     device="cuda")
+    nspec = len(w.spectra)
+
+    def batched():
+        fdas.fdas_correlate_batched(specs, offs, nspec, bank, K, M, L, planes, ws)
+
+    def plain():
+        for b in range(nspec):
+            n = int(o[b + 1] - o[b])
+            fdas.fdas_correlate_ex(specs[o[b]:o[b + 1]], n, bank, K, M, L,
+                                   planes[K * o[b]:K * o[b + 1]], 0)
+
+    batched()
+    ms_b = _timed(torch, batched, steps)
+    plain()
+    ms_p = _timed(torch, plain, steps)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batched()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        batched()
+    g.replay()
+    ms_g = _timed(torch, g.replay, steps)
+    pts = K * int(o[-1])
+    out = {"workload": f"{nspec} ragged spectra (2^18..2^21 bins, sum {int(o[-1])}), {K} templates "
+                       f"x {M} taps, segment {L}",
+           "points": pts,
+           "batched_ms": ms_b, "batched_points_per_s": pts / ms_b * 1e3,
+           "graph_replay_ms": ms_g, "graph_points_per_s": pts / ms_g * 1e3,
+           "plain_loop_ms": ms_p, "plain_loop_points_per_s": pts / ms_p * 1e3,
+           "speedup_batched_vs_plain": ms_p / ms_b}
+    del specs, planes, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_fwd_bwd(fdas, torch, steps: int):
+    """2^20 bins, 85 x 128 taps, segment 2048: forward alone vs forward plus
+    the adjoint (gradients w.r.t. the spectrum and the taps, w ~ U(0,1))."""
+    import fdas_synth as syn
+    w = syn.workload(4)
+    K, M, L = w.K, w.M, w.L
+    N = len(w.spectra[0])
+    spec = torch.from_numpy(w.spectra[0]).cuda()
+    _, bank = fdas.make_bank(w.zmax, w.dz, M, L)
+    wt = torch.from_numpy(syn.loss_weights(4, K, N)).cuda()
+    plane = torch.empty((K, N), dtype=torch.float32, device="cuda")
+    gs = torch.empty(N, dtype=torch.complex64, device="cuda")
+    gt = torch.empty((K, M), dtype=torch.complex64, device="cuda")
+    ws = torch.empty(fdas.fdas_backward_workspace_bytes(N, K, M, L, 0), dtype=torch.uint8,
+                     device="cuda")
+
+    def fwd():
+        fdas.fdas_correlate_ex(spec, N, bank, K, M, L, plane, 0)
+
+    def bwd():
+        fdas.fdas_correlate_backward(spec, N, bank, K, M, L, wt, gs, gt, ws)
+
+    def bwd_spec_only():
+        fdas.fdas_correlate_backward(spec, N, bank, K, M, L, wt, gs, None, ws)
+
+    fwd(); bwd(); bwd_spec_only()
+    ms_f = _timed(torch, fwd, steps)
+    ms_b = _timed(torch, bwd, steps)
+    ms_bs = _timed(torch, bwd_spec_only, steps)
+    pts = K * N
+    out = {"workload": f"2^20 bins, {K} templates x {M} taps, segment {L}",
+           "points": pts,
+           "forward_ms": ms_f, "forward_points_per_s": pts / ms_f * 1e3,
+           "backward_ms": ms_b, "backward_spec_only_ms": ms_bs,
+           "fwd_bwd_points_per_s": pts / (ms_f + ms_b) * 1e3,
+           "fwd_bwd_over_fwd_time": (ms_f + ms_b) / ms_f}
+    del spec, wt, plane, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--L", default="2048,4096", help="segment lengths to time")
-    ap.add_argument("--zchunk", type=int, default=0, help="templates per workgroup (0 = default)")
+    ap.add_argument("--grid", type=int, default=0,
+                    help="persistent workgroups (0 = as many as the device holds resident)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched and forward+backward comparisons")
+    ap.add_argument("--extra-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one plain device copy of BYTES (reference for HBM counters)")
     args = ap.parse_args()
@@ -157,7 +273,7 @@ def main() -> int:
     for L in [int(x) for x in args.L.split(",")]:
         taps, bank = fdas.make_bank(w.zmax, w.dz, M, L, device=dev)
         ms = time_forward(fdas, torch, spec, N, bank, K, M, L, plane, args.steps, args.warmup,
-                          args.zchunk)
+                          args.grid)
         per_L[L] = ms
         print(f"# L={L}: {ms:.4f} ms/step, {K * N / ms / 1e9:.4f} Tpoints/s",
               file=sys.stderr, flush=True)
@@ -193,13 +309,20 @@ def main() -> int:
         "config": {"workload": f"2^21-bin spectrum, {K} templates (z=-84..84 step 2) x {M} "
                                f"taps, segment L={L}",
                    "bins": N, "templates": K, "taps": M, "segment": L,
-                   "zchunk": args.zchunk or "default"},
+                   "grid": args.grid or "resident"},
         "roofline": roof,
         "roofline_other": other,
         "segment_lengths_ms": {str(k): v for k, v in per_L.items()},
         "algorithmic_bytes_per_launch": bytes_,
         "algorithmic_flops_per_launch": flops,
     }
+    del plane
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        out["batched"] = bench_batched(fdas, torch, args.extra_steps)
+        print(f"# batched: {json.dumps(out['batched'])}", file=sys.stderr, flush=True)
+        out["fwd_bwd"] = bench_fwd_bwd(fdas, torch, args.extra_steps)
+        print(f"# fwd_bwd: {json.dumps(out['fwd_bwd'])}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec_np, w.zmax, w.dz, M, K, args.cpu_seconds)
     print(json.dumps(out), flush=True)

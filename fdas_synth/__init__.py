@@ -32,11 +32,15 @@ Workloads (seed = workload number, numpy PCG64):
      z~U[-190,190]; 201 templates x 512 taps, segment 8192.
 
 Draw order within a spectrum: noise real parts, noise imaginary parts, then
-signal parameters.  For ragged workloads all lengths are drawn first.
+signal parameters.  For ragged workloads the lengths are drawn first from the
+workload's stream; spectrum b then draws from its own stream, seeded with
+(workload number, b), so spectra can be generated in parallel.
 """
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -151,20 +155,23 @@ def workload(number: int, L: int | None = None, nspec: int | None = None,
             lens = lens[:nspec]
         if length_scale != 1.0:
             lens = np.maximum((lens * length_scale).astype(np.int64), 1)
-        specs, allsigs = [], []
-        for nb in lens:
-            nb = int(nb)
+        def one(b, nb, nsig=nsig, zr=zr, M=M):
+            g = np.random.default_rng([number, b])
 
-            def sig_fn(g, n, nsig=nsig, zr=zr):
+            def sig_fn(g, n):
                 if nsig == 1:
                     r = g.uniform(0.05, 0.95) * n
                     z = g.uniform(-zr, zr)
                     return [(amp, g.uniform(0.0, 2.0 * np.pi), r, z)]
                 return _separated(g, nsig, 0.05 * n, 0.95 * n, 2 * M, -zr, zr, amp)
 
-            s, sg = _spectrum(rng, nb, sig_fn)
-            specs.append(s)
-            allsigs.append(sg)
+            return _spectrum(g, int(nb), sig_fn)
+
+        workers = max(1, min(16, os.cpu_count() or 1))
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            done = list(ex.map(lambda bn: one(*bn), enumerate(lens)))
+        specs = [d[0] for d in done]
+        allsigs = [d[1] for d in done]
         name = (f"{len(specs)} ragged spectra, {int(2*zmax/2)+1} templates x {M} taps")
         return Workload(number, specs, zmax, 2.0, M, L or Ld, allsigs, name)
     if number == 4:

@@ -136,11 +136,13 @@ int fdas_correlate(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf32 *bank_d
                    int K, int M, int L, float *plane_dev, hipStream_t stream);
 
 /*
- * Same as fdas_correlate with an explicit launch shape, for tuning:
- * zchunk templates per workgroup (1..K; 0 = library default).
+ * Same as fdas_correlate with an explicit launch shape, for tuning: grid
+ * persistent workgroups (0 = as many as the device holds resident, the
+ * default; at most 2^20).  The (segment, template) work is split into
+ * `grid` contiguous ranges; the plane does not depend on grid.
  */
 int fdas_correlate_ex(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf32 *bank_dev,
-                      int K, int M, int L, float *plane_dev, int zchunk,
+                      int K, int M, int L, float *plane_dev, int grid,
                       hipStream_t stream);
 
 /* Bytes of device workspace fdas_correlate_batched needs for nspec spectra
@@ -172,12 +174,12 @@ int fdas_correlate_batched(const fdas_cf32 *specs_dev, const int64_t *offsets_de
                            const fdas_cf32 *bank_dev, int K, int M, int L, float *planes_dev,
                            void *ws_dev, size_t ws_bytes, hipStream_t stream);
 
-/* Same with an explicit launch shape: zchunk templates per work item
- * (0 = all K) and grid persistent workgroups (0 = fill the device). */
+/* Same with an explicit number of persistent workgroups (0 = as many as the
+ * device holds resident; at most 2^20). */
 int fdas_correlate_batched_ex(const fdas_cf32 *specs_dev, const int64_t *offsets_dev,
                               int nspec, const fdas_cf32 *bank_dev, int K, int M, int L,
-                              float *planes_dev, int zchunk, int grid, void *ws_dev,
-                              size_t ws_bytes, hipStream_t stream);
+                              float *planes_dev, int grid, void *ws_dev, size_t ws_bytes,
+                              hipStream_t stream);
 
 /* Bytes of device workspace for fdas_correlate_backward(_ex) with the same
  * (N, K, M, L, zchunk; 0 = default), a multiple of 256; 0 for an invalid

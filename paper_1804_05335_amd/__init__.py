@@ -37,13 +37,14 @@ def prepare_bank(taps, L: int):
     return bank
 
 
-def correlate(spec, bank, K: int, M: int, L: int, plane=None, zchunk: int = 0):
-    """f-fdot power plane [K][N] float32 of one complex64 spectrum."""
+def correlate(spec, bank, K: int, M: int, L: int, plane=None, grid: int = 0):
+    """f-fdot power plane [K][N] float32 of one complex64 spectrum
+    (grid: persistent workgroups, 0 = fill the device)."""
     import torch
     N = spec.numel()
     if plane is None:
         plane = torch.empty((K, N), dtype=torch.float32, device=spec.device)
-    fdas_correlate_ex(spec, N, bank, K, M, L, plane, zchunk)
+    fdas_correlate_ex(spec, N, bank, K, M, L, plane, grid)
     return plane
 
 
@@ -60,7 +61,7 @@ def pack(spectra, device="cuda"):
 
 
 def correlate_batched(specs, offsets, bank, K: int, M: int, L: int, planes=None, ws=None,
-                      zchunk: int = 0, grid: int = 0):
+                      grid: int = 0):
     """Planes of packed spectra in one persistent launch.
 
     ``offsets`` is the device int64 tensor of nspec + 1 offsets; plane b is
@@ -77,5 +78,5 @@ def correlate_batched(specs, offsets, bank, K: int, M: int, L: int, planes=None,
     if ws is None:
         ws = torch.empty(max(fdas_batched_workspace_bytes(nspec), 1), dtype=torch.uint8,
                          device=specs.device)
-    fdas_correlate_batched_ex(specs, offsets, nspec, bank, K, M, L, planes, zchunk, grid, ws)
+    fdas_correlate_batched_ex(specs, offsets, nspec, bank, K, M, L, planes, grid, ws)
     return planes

@@ -40,7 +40,7 @@ SIGNATURES = [
     ("fdas_correlate_ex", _I, [_P, _I64, _P, _I, _I, _I, _P, _I, _P]),
     ("fdas_batched_workspace_bytes", _SZ, [_I]),
     ("fdas_correlate_batched", _I, [_P, _P, _I, _P, _I, _I, _I, _P, _P, _SZ, _P]),
-    ("fdas_correlate_batched_ex", _I, [_P, _P, _I, _P, _I, _I, _I, _P, _I, _I, _P, _SZ, _P]),
+    ("fdas_correlate_batched_ex", _I, [_P, _P, _I, _P, _I, _I, _I, _P, _I, _P, _SZ, _P]),
     ("fdas_backward_workspace_bytes", _SZ, [_I64, _I, _I, _I, _I]),
     ("fdas_correlate_backward", _I, [_P, _I64, _P, _I, _I, _I, _P, _P, _P, _P, _SZ, _P]),
     ("fdas_correlate_backward_ex", _I, [_P, _I64, _P, _I, _I, _I, _P, _P, _P, _I, _P, _SZ, _P]),
@@ -169,13 +169,13 @@ def fdas_correlate(spec, N: int, bank, K: int, M: int, L: int, plane, stream=Non
                                 _stream(stream, spec)), "fdas_correlate")
 
 
-def fdas_correlate_ex(spec, N: int, bank, K: int, M: int, L: int, plane, zchunk: int,
+def fdas_correlate_ex(spec, N: int, bank, K: int, M: int, L: int, plane, grid: int,
                       stream=None) -> None:
     import torch
     _require(spec, torch.complex64, "spec", N)
     _require(bank, torch.complex64, "bank", fdas_bank_elems(K, L))
     _require(plane, torch.float32, "plane", K * N)
-    _check(lib().fdas_correlate_ex(_ptr(spec), N, _ptr(bank), K, M, L, _ptr(plane), zchunk,
+    _check(lib().fdas_correlate_ex(_ptr(spec), N, _ptr(bank), K, M, L, _ptr(plane), grid,
                                    _stream(stream, spec)), "fdas_correlate_ex")
 
 
@@ -185,11 +185,11 @@ def fdas_batched_workspace_bytes(nspec: int) -> int:
 
 def fdas_correlate_batched(specs, offsets, nspec: int, bank, K: int, M: int, L: int, planes,
                            ws, stream=None) -> None:
-    fdas_correlate_batched_ex(specs, offsets, nspec, bank, K, M, L, planes, 0, 0, ws, stream)
+    fdas_correlate_batched_ex(specs, offsets, nspec, bank, K, M, L, planes, 0, ws, stream)
 
 
 def fdas_correlate_batched_ex(specs, offsets, nspec: int, bank, K: int, M: int, L: int, planes,
-                              zchunk: int, grid: int, ws, stream=None) -> None:
+                              grid: int, ws, stream=None) -> None:
     import torch
     _require(specs, torch.complex64, "specs")
     _require(offsets, torch.int64, "offsets", nspec + 1)
@@ -197,7 +197,7 @@ def fdas_correlate_batched_ex(specs, offsets, nspec: int, bank, K: int, M: int, 
     _require(planes, torch.float32, "planes")
     _require(ws, torch.uint8, "ws", fdas_batched_workspace_bytes(nspec))
     _check(lib().fdas_correlate_batched_ex(_ptr(specs), _ptr(offsets), nspec, _ptr(bank), K, M, L,
-                                           _ptr(planes), zchunk, grid, _ptr(ws),
+                                           _ptr(planes), grid, _ptr(ws),
                                            ws.numel(), _stream(stream, specs)),
            "fdas_correlate_batched")
 

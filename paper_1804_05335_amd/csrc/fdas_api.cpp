@@ -43,6 +43,7 @@ bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 constexpr int kMaxK = 4096;
 constexpr int64_t kMaxN = int64_t(1) << 32;
 constexpr int kMaxSpectra = 1 << 24;
+constexpr int kMaxGrid = 1 << 20;
 
 int check_grid(double zmax, double dz, int* K)
 {
@@ -208,27 +209,24 @@ int fdas_make_templates(double zmax, double dz, int M, int L, fdas_cf32* taps_de
 }
 
 int fdas_correlate_ex(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* bank_dev, int K,
-                      int M, int L, float* plane_dev, int zchunk, hipStream_t stream)
+                      int M, int L, float* plane_dev, int grid, hipStream_t stream)
 {
     int st = check_geometry(K, M, L);
     if (st)
         return st;
     if (N < 0 || N > kMaxN)
         return fail(FDAS_INVALID_ARG, "N = %lld outside [0, 2^32]", (long long)N);
-    if (zchunk < 0 || zchunk > K)
-        return fail(FDAS_INVALID_ARG, "zchunk = %d outside [0, K = %d]", zchunk, K);
+    if (grid < 0 || grid > kMaxGrid)
+        return fail(FDAS_INVALID_ARG, "grid = %d outside [0, %d]", grid, kMaxGrid);
     if (N == 0)
         return ok();
     if (!spec_dev || !bank_dev || !plane_dev)
         return fail(FDAS_INVALID_ARG, "spec_dev, bank_dev and plane_dev must not be NULL");
     if (!aligned(spec_dev, 8) || !aligned(bank_dev, 16) || !aligned(plane_dev, 4))
         return fail(FDAS_INVALID_ARG, "misaligned pointer (spec 8 B, bank 16 B, plane 4 B)");
-    const int64_t nseg = (N + (L - M) - 1) / (L - M);
-    if (zchunk == 0)
-        zchunk = fdas::default_zchunk(nseg, K);
     hipError_t e = fdas::launch_forward(reinterpret_cast<const float2*>(spec_dev), N,
                                         reinterpret_cast<const float2*>(bank_dev), K, M, L,
-                                        plane_dev, zchunk, stream);
+                                        plane_dev, grid, stream);
     if (e != hipSuccess)
         return hip_fail(e, "forward launch");
     return ok();
@@ -250,18 +248,15 @@ size_t fdas_batched_workspace_bytes(int nspec)
 
 int fdas_correlate_batched_ex(const fdas_cf32* specs_dev, const int64_t* offsets_dev, int nspec,
                               const fdas_cf32* bank_dev, int K, int M, int L, float* planes_dev,
-                              int zchunk, int grid, void* ws_dev, size_t ws_bytes,
-                              hipStream_t stream)
+                              int grid, void* ws_dev, size_t ws_bytes, hipStream_t stream)
 {
     int st = check_geometry(K, M, L);
     if (st)
         return st;
     if (nspec < 0 || nspec > kMaxSpectra)
         return fail(FDAS_INVALID_ARG, "nspec = %d outside [0, %d]", nspec, kMaxSpectra);
-    if (zchunk < 0 || zchunk > K)
-        return fail(FDAS_INVALID_ARG, "zchunk = %d outside [0, K = %d]", zchunk, K);
-    if (grid < 0 || grid > (1 << 20))
-        return fail(FDAS_INVALID_ARG, "grid = %d outside [0, 2^20]", grid);
+    if (grid < 0 || grid > kMaxGrid)
+        return fail(FDAS_INVALID_ARG, "grid = %d outside [0, %d]", grid, kMaxGrid);
     if (nspec == 0)
         return ok();
     if (!specs_dev || !offsets_dev || !bank_dev || !planes_dev || !ws_dev)
@@ -273,12 +268,10 @@ int fdas_correlate_batched_ex(const fdas_cf32* specs_dev, const int64_t* offsets
     if (ws_bytes < fdas_batched_workspace_bytes(nspec))
         return fail(FDAS_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", ws_bytes,
                     fdas_batched_workspace_bytes(nspec));
-    if (zchunk == 0)
-        zchunk = K;
     hipError_t e = fdas::launch_batched(reinterpret_cast<const float2*>(specs_dev), offsets_dev,
                                         nspec, reinterpret_cast<const float2*>(bank_dev), K, M,
-                                        L, planes_dev, zchunk, static_cast<int64_t*>(ws_dev),
-                                        grid, stream);
+                                        L, planes_dev, static_cast<int64_t*>(ws_dev), grid,
+                                        stream);
     if (e != hipSuccess)
         return hip_fail(e, "batched launch");
     return ok();
@@ -289,7 +282,7 @@ int fdas_correlate_batched(const fdas_cf32* specs_dev, const int64_t* offsets_de
                            void* ws_dev, size_t ws_bytes, hipStream_t stream)
 {
     return fdas_correlate_batched_ex(specs_dev, offsets_dev, nspec, bank_dev, K, M, L,
-                                     planes_dev, 0, 0, ws_dev, ws_bytes, stream);
+                                     planes_dev, 0, ws_dev, ws_bytes, stream);
 }
 
 namespace {

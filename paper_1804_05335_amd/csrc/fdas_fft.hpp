@@ -262,10 +262,15 @@ __device__ __forceinline__ void load_twiddles(float2 (&tw)[NTW], const float2* _
 // multiplier pre[m] (MODE0: kMul or kMulConj) into its first butterfly
 // stage; later passes fuse their twiddles the same way.  Exchanges
 // ping-pong between the two LDS buffers (one barrier each).
-template <int L, int E, bool INV, int MODE0, int NS, int OFF, int NTW, int R, int... Rest>
+struct NoHook {
+    __device__ void operator()() const {}
+};
+
+template <int L, int E, bool INV, int MODE0, int NS, int OFF, int NTW, class Hook, int R,
+          int... Rest>
 __device__ __forceinline__ void run_passes(const float2 (&in)[E], const float2 (&pre)[E],
                                            float2 (&v)[E], float2*& lds_a, float2*& lds_b,
-                                           const float2 (&tw)[NTW], int t)
+                                           const float2 (&tw)[NTW], int t, Hook& hook)
 {
     constexpr int T = L / E, NB = E / R;
     constexpr bool LAST = sizeof...(Rest) == 0;
@@ -304,6 +309,8 @@ __device__ __forceinline__ void run_passes(const float2 (&in)[E], const float2 (
                 lds_a[lds_pad(idxD + i * NS)] = x[i];
         }
     }
+    if constexpr (NS == 1)
+        hook();     // `in` and `pre` are no longer read: their registers may be reloaded
     if constexpr (!LAST) {
         __syncthreads();
 #pragma unroll
@@ -312,8 +319,9 @@ __device__ __forceinline__ void run_passes(const float2 (&in)[E], const float2 (
         float2* tmp = lds_a;
         lds_a = lds_b;
         lds_b = tmp;
-        run_passes<L, E, INV, kNoMul, NS * R, OFF + (NS > 1 ? NB * (R - 1) : 0), NTW, Rest...>(
-            v, pre, v, lds_a, lds_b, tw, t);
+        NoHook none;
+        run_passes<L, E, INV, kNoMul, NS * R, OFF + (NS > 1 ? NB * (R - 1) : 0), NTW, NoHook,
+                   Rest...>(v, pre, v, lds_a, lds_b, tw, t, none);
     }
 }
 
@@ -337,14 +345,26 @@ struct FFT<L, E, Radices<Rs...>> {
     __device__ static void run(float2 (&v)[E], float2*& lds_a, float2*& lds_b,
                                const float2 (&tw)[NTW], int t)
     {
-        run_passes<L, E, INV, kNoMul, 1, 0, NTW, Rs...>(v, v, v, lds_a, lds_b, tw, t);
+        NoHook none;
+        run_passes<L, E, INV, kNoMul, 1, 0, NTW, NoHook, Rs...>(v, v, v, lds_a, lds_b, tw, t, none);
     }
     // v = transform of in[m] * pre[m] (MODE kMul) or in[m] * conj(pre[m]) (kMulConj)
     template <bool INV, int MODE>
     __device__ static void run_mul(const float2 (&in)[E], const float2 (&pre)[E], float2 (&v)[E],
                                    float2*& lds_a, float2*& lds_b, const float2 (&tw)[NTW], int t)
     {
-        run_passes<L, E, INV, MODE, 1, 0, NTW, Rs...>(in, pre, v, lds_a, lds_b, tw, t);
+        NoHook none;
+        run_passes<L, E, INV, MODE, 1, 0, NTW, NoHook, Rs...>(in, pre, v, lds_a, lds_b, tw, t,
+                                                              none);
+    }
+    // as run_mul; hook() runs once the first pass has consumed `in` and `pre`
+    template <bool INV, int MODE, class Hook>
+    __device__ static void run_mul_hook(const float2 (&in)[E], const float2 (&pre)[E],
+                                        float2 (&v)[E], float2*& lds_a, float2*& lds_b,
+                                        const float2 (&tw)[NTW], int t, Hook& hook)
+    {
+        run_passes<L, E, INV, MODE, 1, 0, NTW, Hook, Rs...>(in, pre, v, lds_a, lds_b, tw, t,
+                                                            hook);
     }
 };
 

@@ -14,15 +14,16 @@ std::complex<double> response(double q, double z);
 hipError_t launch_prepare_bank(const float2* taps, int K, int M, int L, float2* bank,
                                hipStream_t s);
 
-// Fused forward correlation of one spectrum; zchunk templates per workgroup.
+// Fused forward correlation of one spectrum on `grid` persistent workgroups
+// (0 = as many as the device holds resident).
 hipError_t launch_forward(const float2* spec, int64_t N, const float2* bank, int K, int M,
-                          int L, float* plane, int zchunk, hipStream_t s);
+                          int L, float* plane, int grid, hipStream_t s);
 
 // Batched ragged correlation: segment scan into segpre[nspec + 1] (device
 // workspace), then the persistent kernel on `grid` workgroups (0 = fill the
 // device at full occupancy).
 hipError_t launch_batched(const float2* specs, const int64_t* offsets, int nspec,
-                          const float2* bank, int K, int M, int L, float* planes, int zchunk,
+                          const float2* bank, int K, int M, int L, float* planes,
                           int64_t* segpre, int grid, hipStream_t s);
 
 // Adjoint: window kernel into partA [nzc][nwin][L] / partT [nwin][K][M], then
@@ -31,7 +32,5 @@ hipError_t launch_backward(const float2* spec, int64_t N, const float2* bank, in
                           int L, const float* dLdP, float2* grad_spec, float2* grad_taps,
                           int zchunk, float2* partA, float2* partT, hipStream_t s);
 
-// Default templates-per-workgroup for a problem (occupancy heuristic).
-int default_zchunk(int64_t nseg, int K);
 
 }  // namespace fdas

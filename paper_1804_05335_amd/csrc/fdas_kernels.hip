@@ -1,5 +1,6 @@
-// HIP kernels for gfx950: template-bank preparation and the fused forward
-// overlap-save correlation (Sec. 3, Fig. 1; Sec. 4.2).
+// HIP kernels for gfx950: template-bank preparation, the fused forward
+// overlap-save correlation (Sec. 3, Fig. 1; Sec. 4.2), its batched ragged
+// form, and the adjoint.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -67,17 +68,16 @@ hipError_t launch_prepare_bank(const float2* taps, int K, int M, int L, float2* 
 
 // ---- fused forward correlation ---------------------------------------------
 //
-// One work item = (segment s of a spectrum, chunk [z0, z1) of templates).
-// Segment s produces the B = L - M outputs [s B, s B + B) from the window
-// of input bins [s B - M/2, s B - M/2 + L) (zero outside [0, N)):
+// Segment s produces the B = L - M outputs [s B, s B + B) from the window of
+// input bins [s B - M/2, s B - M/2 + L) (zero outside [0, N)):
 //   1. coalesced window load (lane t: positions t + T m);
-//   2. forward FFT of the window (kept in registers for all templates);
-//   3. for each template z of the chunk: multiply by H_z (natural order,
-//      next H_z prefetched), inverse FFT, |.|^2, and non-temporal stores of
-//      the B valid outputs to plane[z][s B + u].
+//   2. forward FFT of the window (kept in registers for all its templates);
+//   3. per template z: multiply by H_z (natural order, fused into the first
+//      inverse pass), inverse FFT, |.|^2, non-temporal stores of the B valid
+//      outputs to plane[z][s B + u].
 // Nothing but the valid plane values reaches HBM (Sec. 4.2 first paragraph).
-// The LDS ping-pong buffers la/lb keep alternating across calls, so
-// consecutive work items of one workgroup need no extra barrier.
+// The LDS ping-pong buffers la/lb keep alternating across calls, so a
+// workgroup's consecutive work needs no extra barrier.
 template <int L>
 struct Fwd {
     static constexpr int E = Geometry<L>::E;
@@ -85,7 +85,8 @@ struct Fwd {
     static constexpr int T = F::T;
     static constexpr int NTW = F::NTW;
 
-    __device__ static void load_row(float2 (&H)[E], const float2* __restrict__ bank, int row, int t)
+    __device__ static void load_row(float2 (&H)[E], const float2* __restrict__ bank, int row,
+                                    int t)
     {
         const float2* h = bank + (int64_t)row * L + t;
 #pragma unroll
@@ -93,74 +94,173 @@ struct Fwd {
             H[m] = h[T * m];
     }
 
-    // inverse transform of X * H_z, then |.|^2 of the valid outputs to row z
-    __device__ static void one_template(const float2 (&X)[E], const float2 (&H)[E], int64_t N,
-                                        int M, int64_t out0, int z, float* __restrict__ plane,
-                                        const float2 (&tw)[NTW], float2*& la, float2*& lb, int t)
+    __device__ static void load_window(float2 (&X)[E], const float2* __restrict__ spec,
+                                       int64_t N, int64_t in0, int t)
     {
-        const int B = L - M;
-        float2 v[E];
-        F::template run_mul<true, kMul>(X, H, v, la, lb, tw, t);
-        float* row = plane + (int64_t)z * N + out0;
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const int u = t + T * m - M / 2;
-            if (u >= 0 && u < B && out0 + u < N) {
-                const float p = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
-                __builtin_nontemporal_store(p, row + (unsigned)u);
-            }
-        }
-    }
-
-    // K: rows in the bank before the twiddle row (row K is always readable,
-    // so the H prefetch of the next template is unconditional)
-    __device__ static void item(const float2* __restrict__ spec, int64_t N,
-                                const float2* __restrict__ bank, int K, int M, int64_t s, int z0,
-                                int z1, float* __restrict__ plane, const float2 (&tw)[NTW],
-                                float2*& la, float2*& lb, int t)
-    {
-        const int B = L - M;
-        const int64_t out0 = s * B;
-        const int64_t in0 = out0 - M / 2;
-
-        float2 X[E];
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int64_t idx = in0 + t + T * m;
             X[m] = (idx >= 0 && idx < N) ? spec[idx] : make_float2(0.f, 0.f);
         }
+    }
+
+    // Templates [z0, z1) of segment s.  H holds bank row z0 on entry; each
+    // template's successor row (row 0 after the last template, ready for the
+    // next segment) is loaded into H as soon as the first inverse pass has
+    // consumed it, so the load overlaps the rest of the transform without a
+    // second register buffer.
+    __device__ static void item(const float2* __restrict__ spec, int64_t N,
+                                const float2* __restrict__ bank, int K, int M, int64_t s, int z0,
+                                int z1, float* __restrict__ plane, const float2 (&tw)[NTW],
+                                float2*& la, float2*& lb, int t, float2 (&H)[E])
+    {
+        const int B = L - M;
+        const int64_t out0 = s * B;
+        float2 X[E];
+        load_window(X, spec, N, out0 - M / 2, t);
         F::template run<false>(X, la, lb, tw, t);
 
-        // two H buffers, two templates per trip: the prefetch of the next
-        // template's row never needs a register copy
-        float2 Ha[E], Hb[E];
-        load_row(Ha, bank, z0, t);
-        for (int z = z0; z < z1; z += 2) {
-            load_row(Hb, bank, min(z + 1, K), t);
-            one_template(X, Ha, N, M, out0, z, plane, tw, la, lb, t);
-            load_row(Ha, bank, min(z + 2, K), t);
-            if (z + 1 < z1)
-                one_template(X, Hb, N, M, out0, z + 1, plane, tw, la, lb, t);
+        for (int z = z0; z < z1; ++z) {
+            float2 v[E];
+            const int znext = z + 1 == K ? 0 : z + 1;
+            auto next = [&]() { load_row(H, bank, znext, t); };
+            F::template run_mul_hook<true, kMul>(X, H, v, la, lb, tw, t, next);
+            float* row = plane + (int64_t)z * N + out0;
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int u = t + T * m - M / 2;
+                if (u >= 0 && u < B && out0 + u < N) {
+                    const float p = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
+                    __builtin_nontemporal_store(p, row + (unsigned)u);
+                }
+            }
         }
     }
 };
 
-// One spectrum: grid (segments, template chunks).
+// Work partition of the persistent kernels: the flattened (segment,
+// template) items [0, total) are split into gridDim.x contiguous ranges, one
+// per workgroup, so every workgroup gets the same number of templates (+-1)
+// and recomputes a window FFT only where its range enters a segment.
+__device__ __forceinline__ void item_range(int64_t total, int64_t& i0, int64_t& i1)
+{
+    const int64_t P = gridDim.x, w = blockIdx.x;
+    i0 = total * w / P;
+    i1 = total * (w + 1) / P;
+}
+
+// One spectrum of N bins in nseg segments; persistent grid.
 template <int L>
-__global__ __launch_bounds__(Fwd<L>::T) void forward_kernel(
+__global__ __launch_bounds__(Fwd<L>::T, 2) void forward_kernel(
     const float2* __restrict__ spec, int64_t N, const float2* __restrict__ bank, int K, int M,
-    int zchunk, float* __restrict__ plane)
+    int64_t nseg, float* __restrict__ plane)
 {
     using W = Fwd<L>;
     __shared__ float2 lds[2][LdsSize<L>::value];
+    int64_t i, i1;
+    item_range(nseg * K, i, i1);
+    if (i >= i1)
+        return;     // uniform across the workgroup, before any barrier
     const int t = threadIdx.x;
     float2 tw[W::NTW];
     W::F::twiddles(tw, bank + (int64_t)K * L, t);
     float2* la = lds[0];
     float2* lb = lds[1];
-    const int z0 = blockIdx.y * zchunk;
-    const int z1 = min(K, z0 + zchunk);
-    W::item(spec, N, bank, K, M, blockIdx.x, z0, z1, plane, tw, la, lb, t);
+    float2 H[W::E];
+    W::load_row(H, bank, (int)(i % K), t);
+    while (i < i1) {
+        const int64_t s = i / K;
+        const int zs = (int)(i - s * K);
+        const int ze = (int)min<int64_t>(K, zs + (i1 - i));
+        W::item(spec, N, bank, K, M, s, zs, ze, plane, tw, la, lb, t, H);
+        i += ze - zs;
+    }
+}
+
+// ---- batched ragged correlation --------------------------------------------
+//
+// Spectra b = 0..nspec-1 are packed back to back: spectrum b is
+// specs[offsets[b] .. offsets[b+1]) and its plane starts at
+// planes + K * offsets[b] ([K][N_b] row-major).  A single-workgroup scan
+// turns the lengths into segment counts and their prefix sums segpre[0..nspec]
+// (segpre[nspec] = total segments); the persistent kernel then splits the
+// flattened (segment, template) items of all spectra into contiguous ranges,
+// so one launch of a fixed grid covers any batch and every workgroup reaches
+// the end of its range.
+
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void segment_scan_kernel(
+    const int64_t* __restrict__ offsets, int nspec, int B, int64_t* __restrict__ segpre)
+{
+    __shared__ int64_t part[kScanThreads];
+    __shared__ int64_t carry;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        carry = 0;
+        segpre[0] = 0;
+    }
+    __syncthreads();
+    for (int base = 0; base < nspec; base += kScanThreads) {
+        const int b = base + t;
+        int64_t segs = 0;
+        if (b < nspec) {
+            const int64_t n = offsets[b + 1] - offsets[b];
+            segs = n > 0 ? (n + B - 1) / B : 0;
+        }
+        part[t] = segs;
+        __syncthreads();
+        // Hillis-Steele inclusive scan over the chunk
+        for (int d = 1; d < kScanThreads; d <<= 1) {
+            const int64_t add = t >= d ? part[t - d] : 0;
+            __syncthreads();
+            part[t] += add;
+            __syncthreads();
+        }
+        if (b < nspec)
+            segpre[b + 1] = carry + part[t];
+        __syncthreads();
+        if (t == kScanThreads - 1)
+            carry += part[t];
+        __syncthreads();
+    }
+}
+
+template <int L>
+__global__ __launch_bounds__(Fwd<L>::T, 2) void batched_kernel(
+    const float2* __restrict__ specs, const int64_t* __restrict__ offsets,
+    const int64_t* __restrict__ segpre, int nspec, const float2* __restrict__ bank, int K,
+    int M, float* __restrict__ planes)
+{
+    using W = Fwd<L>;
+    __shared__ float2 lds[2][LdsSize<L>::value];
+    int64_t i, i1;
+    item_range(segpre[nspec] * K, i, i1);
+    if (i >= i1)
+        return;
+    const int t = threadIdx.x;
+    float2 tw[W::NTW];
+    W::F::twiddles(tw, bank + (int64_t)K * L, t);
+    float2* la = lds[0];
+    float2* lb = lds[1];
+    float2 H[W::E];
+    W::load_row(H, bank, (int)(i % K), t);
+    while (i < i1) {
+        const int64_t tile = i / K;
+        const int zs = (int)(i - tile * K);
+        const int ze = (int)min<int64_t>(K, zs + (i1 - i));
+        // spectrum b: the last index with segpre[b] <= tile
+        int lo = 0, hi = nspec - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (segpre[mid] <= tile) lo = mid; else hi = mid - 1;
+        }
+        const int64_t off = offsets[lo];
+        const int64_t Nb = offsets[lo + 1] - off;
+        W::item(specs + off, Nb, bank, K, M, tile - segpre[lo], zs, ze,
+                planes + (int64_t)K * off, tw, la, lb, t, H);
+        i += ze - zs;
+    }
 }
 
 // ---- adjoint (backward) ------------------------------------------------------
@@ -194,14 +294,8 @@ struct Bwd {
     {
         const int B = L - M;
         const int64_t out0 = s * B;
-        const int64_t in0 = out0 - M / 2;
-
         float2 X[E];
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const int64_t idx = in0 + t + T * m;
-            X[m] = (idx >= 0 && idx < N) ? spec[idx] : make_float2(0.f, 0.f);
-        }
+        W::load_window(X, spec, N, out0 - M / 2, t);
         F::template run<false>(X, la, lb, tw, t);
 
         float2 acc[E];
@@ -284,11 +378,10 @@ __global__ void reduce_grad_spec_kernel(const float2* __restrict__ partA, int64_
     if (k >= N)
         return;
     const int B = L - M;
-    const int64_t hi_num = k + M / 2;
-    int64_t s_hi = hi_num / B;
+    int64_t s_hi = (k + M / 2) / B;            // windows with s B - M/2 <= k
     if (s_hi > nwin - 1)
         s_hi = nwin - 1;
-    const int64_t lo_num = k + M / 2 - L;     // windows with s B - M/2 + L > k
+    const int64_t lo_num = k + M / 2 - L;      // windows with s B - M/2 + L > k
     const int64_t s_lo = lo_num < 0 ? 0 : lo_num / B + 1;
     double sr = 0.0, si = 0.0;
     for (int c = 0; c < nzc; ++c)
@@ -318,134 +411,15 @@ __global__ void reduce_grad_taps_kernel(const float2* __restrict__ partT, int64_
     grad[i] = make_float2((float)(sr * inv), (float)(si * inv));
 }
 
-// ---- batched ragged correlation --------------------------------------------
-//
-// Spectra b = 0..nspec-1 are packed back to back: spectrum b is
-// specs[offsets[b] .. offsets[b+1]) and its plane starts at
-// planes + K * offsets[b] ([K][N_b] row-major).  A single-workgroup scan
-// turns the lengths into segment counts and their prefix sums segpre[0..nspec]
-// (segpre[nspec] = total segments); the persistent kernel then walks the work
-// items (tile, template chunk) with a grid-stride loop, so one launch of a
-// fixed grid covers any batch and every wave reaches the loop's end.
+// ---- launchers -------------------------------------------------------------------
 
-constexpr int kScanThreads = 1024;
-
-__global__ __launch_bounds__(kScanThreads) void segment_scan_kernel(
-    const int64_t* __restrict__ offsets, int nspec, int B, int64_t* __restrict__ segpre)
-{
-    __shared__ int64_t part[kScanThreads];
-    __shared__ int64_t carry;
-    const int t = threadIdx.x;
-    if (t == 0) {
-        carry = 0;
-        segpre[0] = 0;
-    }
-    __syncthreads();
-    for (int base = 0; base < nspec; base += kScanThreads) {
-        const int b = base + t;
-        int64_t segs = 0;
-        if (b < nspec) {
-            const int64_t n = offsets[b + 1] - offsets[b];
-            segs = n > 0 ? (n + B - 1) / B : 0;
-        }
-        part[t] = segs;
-        __syncthreads();
-        // Hillis-Steele inclusive scan over the chunk
-        for (int d = 1; d < kScanThreads; d <<= 1) {
-            const int64_t add = t >= d ? part[t - d] : 0;
-            __syncthreads();
-            part[t] += add;
-            __syncthreads();
-        }
-        if (b < nspec)
-            segpre[b + 1] = carry + part[t];
-        __syncthreads();
-        if (t == kScanThreads - 1)
-            carry += part[t];
-        __syncthreads();
-    }
-}
-
-template <int L>
-__global__ __launch_bounds__(Fwd<L>::T) void batched_kernel(
-    const float2* __restrict__ specs, const int64_t* __restrict__ offsets,
-    const int64_t* __restrict__ segpre, int nspec, const float2* __restrict__ bank, int K,
-    int M, int zchunk, float* __restrict__ planes)
-{
-    using W = Fwd<L>;
-    __shared__ float2 lds[2][LdsSize<L>::value];
-    const int t = threadIdx.x;
-    float2 tw[W::NTW];
-    W::F::twiddles(tw, bank + (int64_t)K * L, t);
-    float2* la = lds[0];
-    float2* lb = lds[1];
-    const int nzc = (K + zchunk - 1) / zchunk;
-    const int64_t total = segpre[nspec] * nzc;
-    for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
-        const int64_t tile = it / nzc;
-        const int zc = (int)(it - tile * nzc);
-        // spectrum b: the last index with segpre[b] <= tile
-        int lo = 0, hi = nspec - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (segpre[mid] <= tile) lo = mid; else hi = mid - 1;
-        }
-        const int b = lo;
-        const int64_t off = offsets[b];
-        const int64_t Nb = offsets[b + 1] - off;
-        const int z0 = zc * zchunk;
-        const int z1 = min(K, z0 + zchunk);
-        W::item(specs + off, Nb, bank, K, M, tile - segpre[b], z0, z1, planes + (int64_t)K * off,
-                tw, la, lb, t);
-    }
-}
-
-int default_zchunk(int64_t nseg, int K)
-{
-    // Enough workgroups to fill 256 CUs several times over; each extra chunk
-    // repeats one forward FFT per segment.
-    const int64_t target = 4096;
-    int64_t chunks = (target + nseg - 1) / (nseg > 0 ? nseg : 1);
-    if (chunks < 1) chunks = 1;
-    if (chunks > K) chunks = K;
-    return (int)((K + chunks - 1) / chunks);
-}
-
-template <int L>
-static hipError_t launch_forward_L(const float2* spec, int64_t N, const float2* bank, int K,
-                                   int M, float* plane, int zchunk, hipStream_t s)
-{
-    const int B = L - M;
-    const int64_t nseg = (N + B - 1) / B;
-    const int nzc = (K + zchunk - 1) / zchunk;
-    dim3 grid((unsigned)nseg, (unsigned)nzc);
-    hipLaunchKernelGGL(forward_kernel<L>, grid, dim3(Fwd<L>::T), 0, s, spec, N, bank,
-                       K, M, zchunk, plane);
-    return hipGetLastError();
-}
-
-hipError_t launch_forward(const float2* spec, int64_t N, const float2* bank, int K, int M,
-                          int L, float* plane, int zchunk, hipStream_t s)
-{
-    switch (L) {
-    case 256:  return launch_forward_L<256>(spec, N, bank, K, M, plane, zchunk, s);
-    case 512:  return launch_forward_L<512>(spec, N, bank, K, M, plane, zchunk, s);
-    case 1024: return launch_forward_L<1024>(spec, N, bank, K, M, plane, zchunk, s);
-    case 2048: return launch_forward_L<2048>(spec, N, bank, K, M, plane, zchunk, s);
-    case 4096: return launch_forward_L<4096>(spec, N, bank, K, M, plane, zchunk, s);
-    case 8192: return launch_forward_L<8192>(spec, N, bank, K, M, plane, zchunk, s);
-    default:   return hipErrorInvalidValue;
-    }
-}
-
-// Persistent grid: resident workgroups per CU x CUs, queried once per
-// (device, L) and cached, so later calls (e.g. under graph capture) make no
-// runtime queries.
-template <int L>
-static hipError_t full_grid(int* grid)
+// Resident workgroups of `kernel` on the current device (occupancy x CUs),
+// queried once per (device, kernel) and cached so later calls -- e.g. under
+// graph capture -- make no runtime queries.
+template <class Kern>
+static hipError_t resident_grid(Kern kernel, int threads, std::atomic<int>* cache, int* grid)
 {
     constexpr int kMaxDev = 64;
-    static std::atomic<int> cache[kMaxDev];
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess)
@@ -458,8 +432,8 @@ static hipError_t full_grid(int* grid)
         }
     }
     int per_cu = 0, cus = 0;
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel<L>, Fwd<L>::T,
-                                                          0)) != hipSuccess)
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0)) !=
+        hipSuccess)
         return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
         hipSuccess)
@@ -471,22 +445,55 @@ static hipError_t full_grid(int* grid)
 }
 
 template <int L>
+static hipError_t launch_forward_L(const float2* spec, int64_t N, const float2* bank, int K,
+                                   int M, float* plane, int grid, hipStream_t s)
+{
+    static std::atomic<int> cache[64];
+    const int64_t nseg = (N + (L - M) - 1) / (L - M);
+    if (grid <= 0) {
+        hipError_t e = resident_grid(forward_kernel<L>, Fwd<L>::T, cache, &grid);
+        if (e != hipSuccess)
+            return e;
+    }
+    if ((int64_t)grid > nseg * K)
+        grid = (int)(nseg * K);
+    hipLaunchKernelGGL(forward_kernel<L>, dim3(grid), dim3(Fwd<L>::T), 0, s, spec, N, bank, K,
+                       M, nseg, plane);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward(const float2* spec, int64_t N, const float2* bank, int K, int M,
+                          int L, float* plane, int grid, hipStream_t s)
+{
+    switch (L) {
+    case 256:  return launch_forward_L<256>(spec, N, bank, K, M, plane, grid, s);
+    case 512:  return launch_forward_L<512>(spec, N, bank, K, M, plane, grid, s);
+    case 1024: return launch_forward_L<1024>(spec, N, bank, K, M, plane, grid, s);
+    case 2048: return launch_forward_L<2048>(spec, N, bank, K, M, plane, grid, s);
+    case 4096: return launch_forward_L<4096>(spec, N, bank, K, M, plane, grid, s);
+    case 8192: return launch_forward_L<8192>(spec, N, bank, K, M, plane, grid, s);
+    default:   return hipErrorInvalidValue;
+    }
+}
+
+template <int L>
 static hipError_t launch_batched_L(const float2* specs, const int64_t* offsets, int nspec,
-                                   const float2* bank, int K, int M, float* planes, int zchunk,
+                                   const float2* bank, int K, int M, float* planes,
                                    int64_t* segpre, int grid, hipStream_t s)
 {
+    static std::atomic<int> cache[64];
     if (grid <= 0) {
-        hipError_t e = full_grid<L>(&grid);
+        hipError_t e = resident_grid(batched_kernel<L>, Fwd<L>::T, cache, &grid);
         if (e != hipSuccess)
             return e;
     }
     hipLaunchKernelGGL(batched_kernel<L>, dim3(grid), dim3(Fwd<L>::T), 0, s, specs, offsets,
-                       segpre, nspec, bank, K, M, zchunk, planes);
+                       segpre, nspec, bank, K, M, planes);
     return hipGetLastError();
 }
 
 hipError_t launch_batched(const float2* specs, const int64_t* offsets, int nspec,
-                          const float2* bank, int K, int M, int L, float* planes, int zchunk,
+                          const float2* bank, int K, int M, int L, float* planes,
                           int64_t* segpre, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(segment_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, offsets, nspec,
@@ -495,12 +502,12 @@ hipError_t launch_batched(const float2* specs, const int64_t* offsets, int nspec
     if (e != hipSuccess)
         return e;
     switch (L) {
-    case 256:  return launch_batched_L<256>(specs, offsets, nspec, bank, K, M, planes, zchunk, segpre, grid, s);
-    case 512:  return launch_batched_L<512>(specs, offsets, nspec, bank, K, M, planes, zchunk, segpre, grid, s);
-    case 1024: return launch_batched_L<1024>(specs, offsets, nspec, bank, K, M, planes, zchunk, segpre, grid, s);
-    case 2048: return launch_batched_L<2048>(specs, offsets, nspec, bank, K, M, planes, zchunk, segpre, grid, s);
-    case 4096: return launch_batched_L<4096>(specs, offsets, nspec, bank, K, M, planes, zchunk, segpre, grid, s);
-    case 8192: return launch_batched_L<8192>(specs, offsets, nspec, bank, K, M, planes, zchunk, segpre, grid, s);
+    case 256:  return launch_batched_L<256>(specs, offsets, nspec, bank, K, M, planes, segpre, grid, s);
+    case 512:  return launch_batched_L<512>(specs, offsets, nspec, bank, K, M, planes, segpre, grid, s);
+    case 1024: return launch_batched_L<1024>(specs, offsets, nspec, bank, K, M, planes, segpre, grid, s);
+    case 2048: return launch_batched_L<2048>(specs, offsets, nspec, bank, K, M, planes, segpre, grid, s);
+    case 4096: return launch_batched_L<4096>(specs, offsets, nspec, bank, K, M, planes, segpre, grid, s);
+    case 8192: return launch_batched_L<8192>(specs, offsets, nspec, bank, K, M, planes, segpre, grid, s);
     default:   return hipErrorInvalidValue;
     }
 }
@@ -526,15 +533,15 @@ hipError_t launch_backward(const float2* spec, int64_t N, const float2* bank, in
     const int want_A = grad_spec != nullptr, want_T = grad_taps != nullptr;
     hipError_t e = hipSuccess;
     if (nwin > 0) {
-    switch (L) {
-    case 256:  e = launch_backward_L<256>(spec, N, bank, K, M, zchunk, nwin, dLdP, want_A, want_T, partA, partT, s); break;
-    case 512:  e = launch_backward_L<512>(spec, N, bank, K, M, zchunk, nwin, dLdP, want_A, want_T, partA, partT, s); break;
-    case 1024: e = launch_backward_L<1024>(spec, N, bank, K, M, zchunk, nwin, dLdP, want_A, want_T, partA, partT, s); break;
-    case 2048: e = launch_backward_L<2048>(spec, N, bank, K, M, zchunk, nwin, dLdP, want_A, want_T, partA, partT, s); break;
-    case 4096: e = launch_backward_L<4096>(spec, N, bank, K, M, zchunk, nwin, dLdP, want_A, want_T, partA, partT, s); break;
-    case 8192: e = launch_backward_L<8192>(spec, N, bank, K, M, zchunk, nwin, dLdP, want_A, want_T, partA, partT, s); break;
-    default:   return hipErrorInvalidValue;
-    }
+        switch (L) {
+        case 256:  e = launch_backward_L<256>(spec, N, bank, K, M, zchunk, nwin, dLdP, want_A, want_T, partA, partT, s); break;
+        case 512:  e = launch_backward_L<512>(spec, N, bank, K, M, zchunk, nwin, dLdP, want_A, want_T, partA, partT, s); break;
+        case 1024: e = launch_backward_L<1024>(spec, N, bank, K, M, zchunk, nwin, dLdP, want_A, want_T, partA, partT, s); break;
+        case 2048: e = launch_backward_L<2048>(spec, N, bank, K, M, zchunk, nwin, dLdP, want_A, want_T, partA, partT, s); break;
+        case 4096: e = launch_backward_L<4096>(spec, N, bank, K, M, zchunk, nwin, dLdP, want_A, want_T, partA, partT, s); break;
+        case 8192: e = launch_backward_L<8192>(spec, N, bank, K, M, zchunk, nwin, dLdP, want_A, want_T, partA, partT, s); break;
+        default:   return hipErrorInvalidValue;
+        }
     }
     if (e != hipSuccess)
         return e;

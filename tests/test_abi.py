@@ -112,8 +112,24 @@ def test_validation_happens_before_any_device_call():
     assert L.fdas_correlate(_fake(0x1004), 1000, bk, 85, 256, 2048, pl, None) == _lib.FDAS_INVALID_ARG
     assert L.fdas_correlate(sp, 1000, _fake(0x2008), 85, 256, 2048, pl, None) == _lib.FDAS_INVALID_ARG
     assert L.fdas_correlate(sp, 1000, bk, 85, 256, 2048, _fake(0x3002), None) == _lib.FDAS_INVALID_ARG
-    assert L.fdas_correlate_ex(sp, 1000, bk, 85, 256, 2048, pl, 86, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_correlate_ex(sp, 1000, bk, 85, 256, 2048, pl, (1 << 20) + 1, None) == _lib.FDAS_INVALID_ARG
     assert L.fdas_correlate_ex(sp, 1000, bk, 85, 256, 2048, pl, -1, None) == _lib.FDAS_INVALID_ARG
+    # batched and backward validation
+    ws = _fake(0x4000)
+    assert L.fdas_correlate_batched(sp, _fake(0x5000), 0, None, 85, 256, 2048, None, None, 0, None) == _lib.FDAS_OK
+    assert L.fdas_correlate_batched(sp, _fake(0x5000), -1, bk, 85, 256, 2048, pl, ws, 1 << 20, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_correlate_batched(sp, _fake(0x5000), 4, bk, 85, 256, 2048, pl, ws, 8, None) == _lib.FDAS_WORKSPACE_TOO_SMALL
+    assert L.fdas_correlate_batched(sp, _fake(0x5004), 4, bk, 85, 256, 2048, pl, ws, 1 << 20, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_correlate_batched(sp, None, 4, bk, 85, 256, 2048, pl, ws, 1 << 20, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_correlate_batched(sp, _fake(0x5000), 4, bk, 85, 256, 1000, pl, ws, 1 << 20, None) == _lib.FDAS_UNSUPPORTED
+    wsb = L.fdas_backward_workspace_bytes(4096, 9, 128, 2048, 0)
+    assert wsb > 0 and wsb % 256 == 0
+    assert L.fdas_backward_workspace_bytes(4096, 9, 2048, 2048, 0) == 0
+    assert L.fdas_correlate_backward(sp, 4096, bk, 9, 128, 2048, pl, sp, None, ws, wsb - 256, None) == _lib.FDAS_WORKSPACE_TOO_SMALL
+    assert L.fdas_correlate_backward(sp, 4096, bk, 9, 128, 2048, pl, None, None, ws, wsb, None) == _lib.FDAS_OK
+    assert L.fdas_correlate_backward(sp, 4096, bk, 9, 128, 2048, pl, sp, None, _fake(0x4010), wsb, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_correlate_backward(sp, 4096, bk, 9, 2048, 2048, pl, sp, None, ws, wsb, None) == _lib.FDAS_UNSUPPORTED
+    assert L.fdas_correlate_backward(None, 4096, bk, 9, 128, 2048, pl, sp, None, ws, wsb, None) == _lib.FDAS_INVALID_ARG
     # N = 0 is a no-op that touches nothing, even with NULL buffers
     assert L.fdas_correlate(None, 0, None, 85, 256, 2048, None, None) == _lib.FDAS_OK
     # bank preparation

@@ -44,16 +44,16 @@ def _rel(got, ref):
     return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
 
 
-@pytest.mark.parametrize("L,M,N,zchunk", [(256, 32, 1000, 0), (512, 64, 449, 2), (2048, 256, 3900, 0),
-                                          (256, 128, 300, 1), (1024, 2, 2000, 3)])
-def test_emulated_forward_vs_oracle(emu, L, M, N, zchunk):
+@pytest.mark.parametrize("L,M,N,grid", [(256, 32, 1000, 0), (512, 64, 449, 2), (2048, 256, 3900, 0),
+                                        (256, 128, 300, 1), (1024, 2, 2000, 7), (512, 64, 2000, 40)])
+def test_emulated_forward_vs_oracle(emu, L, M, N, grid):
     K = 3
     A = syn.random_spectrum(L + N, N)
     taps = syn.random_taps(M + K, K, M)
     bank = _bank(emu, taps, L)
     plane = np.full((K, N), np.nan, dtype=np.float32)
     assert emu.fdas_correlate_ex(_p(A), ctypes.c_int64(N), _p(bank), K, M, L, _p(plane),
-                                 zchunk, None) == 0
+                                 grid, None) == 0
     assert _rel(plane, native.power(A, taps)) < TOL
 
 
@@ -87,10 +87,10 @@ def test_emulated_batched_equals_plain(emu):
     emu.fdas_batched_workspace_bytes.restype = ctypes.c_size_t
     wsb = emu.fdas_batched_workspace_bytes(len(lens))
     ws = np.zeros(wsb, dtype=np.uint8)
-    for zc, grid in [(0, 0), (2, 5)]:
+    for grid in (0, 1, 5, 13):
         planes[:] = np.nan
         assert emu.fdas_correlate_batched_ex(_p(packed), _p(offs), len(lens), _p(bank), K, M, L,
-                                             _p(planes), zc, grid, _p(ws), ctypes.c_size_t(wsb),
+                                             _p(planes), grid, _p(ws), ctypes.c_size_t(wsb),
                                              None) == 0
         for b, n in enumerate(lens):
             if n == 0:

@@ -38,9 +38,9 @@ def _views(planes, offs, K):
             for b in range(len(offs) - 1)]
 
 
-@pytest.mark.parametrize("L,zchunk,grid", [(2048, 0, 0), (2048, 7, 0), (1024, 0, 3),
-                                           (4096, 17, 64), (512, 0, 0)])
-def test_batched_bitwise_equals_plain(fd, L, zchunk, grid):
+@pytest.mark.parametrize("L,grid", [(2048, 0), (2048, 7), (1024, 3), (4096, 64), (512, 0),
+                                    (2048, 100000)])
+def test_batched_bitwise_equals_plain(fd, L, grid):
     w = syn.workload(3, nspec=12, length_scale=1 / 64)
     M = w.M if L >= 2 * w.M else L // 4
     taps, bank = fd.make_bank(w.zmax, w.dz, M, L)
@@ -51,7 +51,7 @@ def test_batched_bitwise_equals_plain(fd, L, zchunk, grid):
     spectra.insert(5, torch.from_numpy(syn.random_spectrum(5, 1)))
     spectra.append(torch.from_numpy(syn.random_spectrum(6, L - M)))
     specs, offs = fd.pack(spectra)
-    planes = fd.correlate_batched(specs, offs, bank, K, M, L, zchunk=zchunk, grid=grid)
+    planes = fd.correlate_batched(specs, offs, bank, K, M, L, grid=grid)
     torch.cuda.synchronize()
     for b, view in enumerate(_views(planes, offs, K)):
         if view.shape[1] == 0:
