@@ -368,14 +368,36 @@ struct FFT<L, E, Radices<Rs...>> {
     }
 };
 
-// Geometry per segment length: E values per lane and the radix sequence.
+// Radix sequence for a length-L transform with E values per lane (every
+// radix divides E, their product is L).
+template <int L, int E>
+struct Plan;
+template <> struct Plan<256, 4>   { using R = Radices<4, 4, 4, 4>; };
+template <> struct Plan<512, 8>   { using R = Radices<8, 8, 8>; };
+template <> struct Plan<1024, 8>  { using R = Radices<8, 8, 8, 2>; };
+template <> struct Plan<1024, 16> { using R = Radices<16, 16, 4>; };
+template <> struct Plan<2048, 8>  { using R = Radices<8, 8, 8, 4>; };
+template <> struct Plan<2048, 16> { using R = Radices<16, 16, 8>; };
+template <> struct Plan<4096, 8>  { using R = Radices<8, 8, 8, 8>; };
+template <> struct Plan<4096, 16> { using R = Radices<16, 16, 16>; };
+template <> struct Plan<8192, 8>  { using R = Radices<8, 8, 8, 8, 2>; };
+template <> struct Plan<8192, 16> { using R = Radices<16, 16, 16, 2>; };
+
+// Values per lane of the forward kernels: 16 from L = 1024 on (two LDS
+// exchanges per transform, 256 VGPRs, 2 waves per SIMD), fewer below so a
+// transform still spans at least one full wave.
+#ifndef FDAS_FWD_E
+#define FDAS_FWD_E 16
+#endif
 template <int L>
-struct Geometry;
-template <> struct Geometry<256>  { static constexpr int E = 4;  using R = Radices<4, 4, 4, 4>; };
-template <> struct Geometry<512>  { static constexpr int E = 8;  using R = Radices<8, 8, 8>; };
-template <> struct Geometry<1024> { static constexpr int E = 16; using R = Radices<16, 16, 4>; };
-template <> struct Geometry<2048> { static constexpr int E = 16; using R = Radices<16, 16, 8>; };
-template <> struct Geometry<4096> { static constexpr int E = 16; using R = Radices<16, 16, 16>; };
-template <> struct Geometry<8192> { static constexpr int E = 16; using R = Radices<16, 16, 16, 2>; };
+struct Geometry {
+    static constexpr int E = L <= 256 ? 4 : (L <= 512 ? 8 : FDAS_FWD_E);
+};
+// Values per lane of the adjoint, which keeps four transform-sized arrays
+// live: 8 from L = 512 on.
+template <int L>
+struct BwdGeometry {
+    static constexpr int E = L <= 256 ? 4 : 8;
+};
 
 }  // namespace fdas

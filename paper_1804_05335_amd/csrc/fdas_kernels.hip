@@ -78,10 +78,10 @@ hipError_t launch_prepare_bank(const float2* taps, int K, int M, int L, float2* 
 // Nothing but the valid plane values reaches HBM (Sec. 4.2 first paragraph).
 // The LDS ping-pong buffers la/lb keep alternating across calls, so a
 // workgroup's consecutive work needs no extra barrier.
-template <int L>
+template <int L, int EV = Geometry<L>::E>
 struct Fwd {
-    static constexpr int E = Geometry<L>::E;
-    using F = FFT<L, E, typename Geometry<L>::R>;
+    static constexpr int E = EV;
+    using F = FFT<L, E, typename Plan<L, E>::R>;
     static constexpr int T = F::T;
     static constexpr int NTW = F::NTW;
 
@@ -279,7 +279,7 @@ __global__ __launch_bounds__(Fwd<L>::T, 2) void batched_kernel(
 // are summed in FP64, in a fixed order, by the two reduction kernels.
 template <int L>
 struct Bwd {
-    using W = Fwd<L>;
+    using W = Fwd<L, BwdGeometry<L>::E>;
     using F = typename W::F;
     static constexpr int E = W::E;
     static constexpr int T = W::T;
@@ -349,7 +349,7 @@ struct Bwd {
 };
 
 template <int L>
-__global__ __launch_bounds__(Fwd<L>::T) void backward_kernel(
+__global__ __launch_bounds__(Bwd<L>::T) void backward_kernel(
     const float2* __restrict__ spec, int64_t N, const float2* __restrict__ bank, int K, int M,
     int zchunk, int64_t nwin, const float* __restrict__ dLdP, int want_A, int want_T,
     float2* __restrict__ partA, float2* __restrict__ partT)
@@ -394,21 +394,37 @@ __global__ void reduce_grad_spec_kernel(const float2* __restrict__ partA, int64_
     grad[k] = make_float2((float)sr, (float)si);
 }
 
-// grad_T[z][j] = (1/L) sum_s partT[s][z][j], FP64 in window order.
-__global__ void reduce_grad_taps_kernel(const float2* __restrict__ partT, int64_t nwin, int KM,
-                                        int L, float2* __restrict__ grad)
+// grad_T[z][j] = (1/L) sum_s partT[s][z][j] in FP64.  A block covers
+// kTapsCols consecutive (z, j) entries with kTapsRows lanes each; lane row q
+// sums windows s = q, q + kTapsRows, ... and the rows are then added in
+// order q = 0, 1, ..., so the result is deterministic.
+constexpr int kTapsCols = 64, kTapsRows = 16;
+
+__global__ __launch_bounds__(kTapsCols * kTapsRows) void reduce_grad_taps_kernel(
+    const float2* __restrict__ partT, int64_t nwin, int KM, int L, float2* __restrict__ grad)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= KM)
-        return;
+    __shared__ double part[kTapsRows][kTapsCols][2];
+    const int c = threadIdx.x % kTapsCols, q = threadIdx.x / kTapsCols;
+    const int i = blockIdx.x * kTapsCols + c;
     double sr = 0.0, si = 0.0;
-    for (int64_t s = 0; s < nwin; ++s) {
-        const float2 v = partT[s * KM + i];
-        sr += v.x;
-        si += v.y;
+    if (i < KM)
+        for (int64_t s = q; s < nwin; s += kTapsRows) {
+            const float2 v = partT[s * KM + i];
+            sr += v.x;
+            si += v.y;
+        }
+    part[q][c][0] = sr;
+    part[q][c][1] = si;
+    __syncthreads();
+    if (q == 0 && i < KM) {
+        double tr = 0.0, ti = 0.0;
+        for (int r = 0; r < kTapsRows; ++r) {
+            tr += part[r][c][0];
+            ti += part[r][c][1];
+        }
+        const double inv = 1.0 / (double)L;
+        grad[i] = make_float2((float)(tr * inv), (float)(ti * inv));
     }
-    const double inv = 1.0 / (double)L;
-    grad[i] = make_float2((float)(sr * inv), (float)(si * inv));
 }
 
 // ---- launchers -------------------------------------------------------------------
@@ -519,7 +535,7 @@ static hipError_t launch_backward_L(const float2* spec, int64_t N, const float2*
                                    hipStream_t s)
 {
     const int nzc = (K + zchunk - 1) / zchunk;
-    hipLaunchKernelGGL(backward_kernel<L>, dim3((unsigned)nwin, (unsigned)nzc), dim3(Fwd<L>::T),
+    hipLaunchKernelGGL(backward_kernel<L>, dim3((unsigned)nwin, (unsigned)nzc), dim3(Bwd<L>::T),
                        0, s, spec, N, bank, K, M, zchunk, nwin, dLdP, want_A, want_T, partA,
                        partT);
     return hipGetLastError();
@@ -555,8 +571,8 @@ hipError_t launch_backward(const float2* spec, int64_t N, const float2* bank, in
     }
     if (want_T) {
         const int KM = K * M;
-        hipLaunchKernelGGL(reduce_grad_taps_kernel, dim3((KM + bs - 1) / bs), dim3(bs), 0, s,
-                           partT, nwin, KM, L, grad_taps);
+        hipLaunchKernelGGL(reduce_grad_taps_kernel, dim3((KM + kTapsCols - 1) / kTapsCols),
+                           dim3(kTapsCols * kTapsRows), 0, s, partT, nwin, KM, L, grad_taps);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }

@@ -136,9 +136,9 @@ def test_workload3_full_sampled(fd):
     for b in rng.choice(len(w.spectra), size=8, replace=False):
         n = len(w.spectra[b])
         B = L - w.M
+        bounds = ((np.arange(1, -(-n // B)) * B)[:, None] + np.arange(-2, 3)[None, :]).ravel()
         cols = np.unique(np.concatenate([
-            np.arange(0, 64), np.arange(n - 64, n), rng.integers(0, n, 3000),
-            (np.arange(1, -(-n // B)) * B)[:, None] + np.arange(-2, 3)[None, :]]).ravel())
+            np.arange(0, 64), np.arange(n - 64, n), rng.integers(0, n, 3000), bounds]))
         cols = cols[(cols >= 0) & (cols < n)]
         zi = np.repeat(np.arange(K), len(cols)).astype(np.int32)
         ri = np.tile(cols, K).astype(np.int64)
