@@ -247,6 +247,63 @@ def bench_fwd_bwd(fdas, torch, steps: int):
     return out
 
 
+def bench_workload5(fdas, torch, steps: int):
+    """64 ragged spectra (2^21..2^22 bins), 201 templates x 512 taps, segment
+    8192: batched forward over all spectra, then the gradient w.r.t. every
+    input spectrum for Lw = sum w P.  The plane is freed before the adjoint
+    (which recomputes the segment FFTs instead of reading it), so the plane
+    and dLw/dP -- 2 x 156 GB together, more than the 288 GB of HBM -- are
+    never resident at the same time."""
+    import fdas_synth as syn
+    w = syn.workload(5)
+    packed, o = w.packed()
+    K, M, L = w.K, w.M, w.L
+    nspec = len(w.spectra)
+    specs = torch.from_numpy(packed).cuda()
+    offs = torch.from_numpy(o).cuda()
+    del packed
+    _, bank = fdas.make_bank(w.zmax, w.dz, M, L)
+    total = int(o[-1])
+    planes = torch.empty(K * total, dtype=torch.float32, device="cuda")
+    ws = torch.empty(fdas.fdas_batched_workspace_bytes(nspec), dtype=torch.uint8, device="cuda")
+
+    def fwd():
+        fdas.fdas_correlate_batched(specs, offs, nspec, bank, K, M, L, planes, ws)
+
+    fwd()
+    ms_f = _timed(torch, fwd, steps)
+    del planes
+    torch.cuda.empty_cache()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    wts = torch.rand(K * total, generator=gen, dtype=torch.float32, device="cuda")
+    grads = torch.empty(total, dtype=torch.complex64, device="cuda")
+    nmax = int(max(o[b + 1] - o[b] for b in range(nspec)))
+    bws = torch.empty(fdas.fdas_backward_workspace_bytes(nmax, K, M, L, 0), dtype=torch.uint8,
+                      device="cuda")
+
+    def bwd():
+        for b in range(nspec):
+            n = int(o[b + 1] - o[b])
+            need = fdas.fdas_backward_workspace_bytes(n, K, M, L, 0)
+            fdas.fdas_correlate_backward(specs[o[b]:o[b + 1]], n, bank, K, M, L,
+                                         wts[K * o[b]:K * o[b + 1]], grads[o[b]:o[b + 1]], None,
+                                         bws[:need])
+
+    bwd()
+    ms_b = _timed(torch, bwd, max(1, steps // 2))
+    pts = K * total
+    out = {"workload": f"{nspec} ragged spectra (2^21..2^22 bins, sum {total}), {K} templates x "
+                       f"{M} taps, segment {L}",
+           "points": pts,
+           "forward_batched_ms": ms_f, "forward_points_per_s": pts / ms_f * 1e3,
+           "backward_spec_ms": ms_b, "fwd_bwd_points_per_s": pts / (ms_f + ms_b) * 1e3,
+           "fwd_bwd_over_fwd_time": (ms_f + ms_b) / ms_f}
+    del specs, wts, grads, bws
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -352,6 +409,8 @@ def main() -> int:
         print(f"# batched: {json.dumps(out['batched'])}", file=sys.stderr, flush=True)
         out["fwd_bwd"] = bench_fwd_bwd(fdas, torch, args.extra_steps)
         print(f"# fwd_bwd: {json.dumps(out['fwd_bwd'])}", file=sys.stderr, flush=True)
+        out["large_zmax"] = bench_workload5(fdas, torch, args.extra_steps)
+        print(f"# large_zmax: {json.dumps(out['large_zmax'])}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec_np, w.zmax, w.dz, M, K, args.cpu_seconds)
     print(json.dumps(out), flush=True)

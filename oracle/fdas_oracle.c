@@ -91,6 +91,36 @@ void oracle_correlate(const double *A, int64_t N, const double *T, int K,
                        &Y[2 * ((int64_t)z * N + r) + 1]);
 }
 
+/* grad_A at npts sampled bins k, each from its defining sum:
+ * grad_A[k] = sum_z sum_j T[z][j] g[z][k - e_j], g[z][r] = 2 w[z][r] Y[z][r],
+ * with Y evaluated directly where needed (r in [0, N)).  w is float32 [K][N]. */
+void oracle_grad_spec_points(const double *A, int64_t N, const double *T, int K, int M,
+                             const float *w, const int64_t *ks, int64_t npts, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t p = 0; p < npts; ++p) {
+        const int64_t k = ks[p];
+        double sr = 0.0, si = 0.0;
+        for (int z = 0; z < K; ++z) {
+            const double *Tz = T + 2 * (int64_t)z * M;
+            for (int j = 0; j < M; ++j) {
+                int64_t r = k - ((int64_t)j - (int64_t)(M / 2));
+                if (r < 0 || r >= N)
+                    continue;
+                double yr, yi;
+                corr_point(A, N, Tz, M, r, &yr, &yi);
+                const double s = 2.0 * (double)w[(int64_t)z * N + r];
+                const double gr = s * yr, gi = s * yi;
+                const double tr = Tz[2 * j], ti = Tz[2 * j + 1];
+                sr += tr * gr - ti * gi;
+                si += tr * gi + ti * gr;
+            }
+        }
+        out[2 * p] = sr;
+        out[2 * p + 1] = si;
+    }
+}
+
 /* Gradients of Lw = sum w P.  w is float32 [K][N]; gA is [N], gT is [K][M]
  * (interleaved complex).  Uses a scratch copy of g = 2 w Y. */
 int oracle_grads(const double *A, int64_t N, const double *T, int K, int M,

@@ -41,6 +41,7 @@ def lib():
         L.oracle_correlate.argtypes = [d, i64, d, i32, i32, d]
         L.oracle_grads.argtypes = [d, i64, d, i32, i32, d, d, d]
         L.oracle_grads.restype = ctypes.c_int
+        L.oracle_grad_spec_points.argtypes = [d, i64, d, i32, i32, d, d, i64, d]
         _lib = L
     return _lib
 
@@ -84,6 +85,18 @@ def correlate(A, T) -> np.ndarray:
     K, M = T.shape
     out = np.empty((K, len(A)), dtype=np.complex128)
     lib().oracle_correlate(_p(A), len(A), _p(T), K, M, _p(out))
+    return out
+
+
+def grad_spec_points(A, T, w, ks) -> np.ndarray:
+    """grad_A at the sampled bins ks (complex128), each from its defining sum."""
+    A, T = _c128(A), _c128(T)
+    K, M = T.shape
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    assert w.shape == (K, len(A))
+    ks = np.ascontiguousarray(ks, dtype=np.int64)
+    out = np.empty(len(ks), dtype=np.complex128)
+    lib().oracle_grad_spec_points(_p(A), len(A), _p(T), K, M, _p(w), _p(ks), len(ks), _p(out))
     return out
 
 

@@ -78,3 +78,14 @@ def test_grad_of_linear_weights_is_adjoint_of_correlation():
     assert abs(d - np.real(np.vdot(gA, x))) < 1e-9 * abs(d)
     # and the plain spectrum is unaffected by the synth helpers
     assert syn.random_spectrum(1, 4).dtype == np.complex64
+
+
+def test_c_grad_spec_points_match_full_gradient():
+    # the per-point spectrum gradient (used for sampled checks at full size)
+    # equals the full adjoint at every bin, including both edges
+    A, T, w = _setup(6, N=700, K=4, M=24)
+    w = w.astype(np.float32)
+    gA, _ = direct.grads(A, T, w)
+    ks = np.array([0, 1, 5, 11, 12, 13, 350, 687, 688, 699], dtype=np.int64)
+    got = native.grad_spec_points(A, T, w, ks)
+    assert np.max(np.abs(got - gA[ks])) < 1e-11 * np.max(np.abs(gA))
