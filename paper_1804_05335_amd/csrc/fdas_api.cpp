@@ -291,9 +291,10 @@ int backward_zchunk(int64_t nwin, int K, int zchunk)
 {
     if (zchunk > 0)
         return zchunk;
-    // enough workgroups to fill the device; each chunk adds one partial
-    // gradient window and one recomputed forward FFT per window
-    int64_t chunks = (2048 + (nwin > 0 ? nwin : 1) - 1) / (nwin > 0 ? nwin : 1);
+    // ~4096 workgroups, about 8 rounds of the ~512 resident on 256 CUs, so the
+    // last round's tail stays small; each chunk adds one partial gradient
+    // window and one recomputed forward FFT per window
+    int64_t chunks = (4096 + (nwin > 0 ? nwin : 1) - 1) / (nwin > 0 ? nwin : 1);
     if (chunks < 1) chunks = 1;
     if (chunks > K) chunks = K;
     return (int)((K + chunks - 1) / chunks);

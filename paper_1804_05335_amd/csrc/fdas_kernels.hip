@@ -320,6 +320,9 @@ struct Bwd {
             }
             F::template run<false>(v, la, lb, tw, t);                     // G = FFT(g)
             if (want_A) {
+                // reload H_z (an L2 hit) rather than keep it live across both
+                // transforms: the adjoint is register-bound
+                W::load_row(H, bank, z, t);
 #pragma unroll
                 for (int m = 0; m < E; ++m) {                             // acc += conj(H) G
                     acc[m].x = fmaf(v[m].x, H[m].x, fmaf(v[m].y, H[m].y, acc[m].x));
