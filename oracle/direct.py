@@ -78,3 +78,17 @@ def grads(A, T, w):
     for j in range(M):
         gT[:, j] = gc @ pad[j:j + N]
     return gA, gT
+
+
+def interbinned_power(A, T) -> np.ndarray:
+    """Power plane with interbinning (Sec. 3, eq. f-interp), P2[K][2N]:
+    column 2r is |Y[r]|^2 and column 2r+1 the half-bin estimate
+    |(pi/4)(Y[r] - Y[r+1])|^2, where Y[N] is the same correlation sum one bin
+    past the end (the spectrum is zero outside [0, N))."""
+    A = np.asarray(A, dtype=np.complex128)
+    N = len(A)
+    Y = correlate(np.concatenate([A, [0.0]]), T)          # Y[:, 0..N]
+    P2 = np.empty((Y.shape[0], 2 * N), dtype=np.float64)
+    P2[:, 0::2] = np.abs(Y[:, :N]) ** 2
+    P2[:, 1::2] = np.abs((np.pi / 4) * (Y[:, :N] - Y[:, 1:N + 1])) ** 2
+    return P2

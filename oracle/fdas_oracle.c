@@ -79,6 +79,31 @@ void oracle_power_points(const double *A, int64_t N, const double *T, int K,
     }
 }
 
+/* Interbinned plane (Sec. 3, eq. f-interp) at sampled (z, column) points of
+ * the [K][2N] layout: column 2r is |Y[z][r]|^2, column 2r+1 is
+ * |(pi/4)(Y[z][r] - Y[z][r+1])|^2 with Y[z][N] from the same sum. */
+void oracle_interbin_points(const double *A, int64_t N, const double *T, int K, int M,
+                            const int32_t *zi, const int64_t *ci, int64_t npts, double *out)
+{
+    (void)K;
+    const double q = 0.78539816339744830962; /* pi/4 */
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < npts; ++p) {
+        const double *Tz = T + 2 * (int64_t)zi[p] * M;
+        const int64_t r = ci[p] / 2;
+        double yr, yi;
+        corr_point(A, N, Tz, M, r, &yr, &yi);
+        if ((ci[p] & 1) == 0) {
+            out[p] = yr * yr + yi * yi;
+        } else {
+            double nr, ni;
+            corr_point(A, N, Tz, M, r + 1, &nr, &ni);
+            const double dr = q * (yr - nr), di = q * (yi - ni);
+            out[p] = dr * dr + di * di;
+        }
+    }
+}
+
 /* Complex correlation Y (interleaved) for all z, r. */
 void oracle_correlate(const double *A, int64_t N, const double *T, int K,
                       int M, double *Y)

@@ -42,6 +42,7 @@ def lib():
         L.oracle_grads.argtypes = [d, i64, d, i32, i32, d, d, d]
         L.oracle_grads.restype = ctypes.c_int
         L.oracle_grad_spec_points.argtypes = [d, i64, d, i32, i32, d, d, i64, d]
+        L.oracle_interbin_points.argtypes = [d, i64, d, i32, i32, d, d, i64, d]
         _lib = L
     return _lib
 
@@ -77,6 +78,17 @@ def power_points(A, T, zi, ri) -> np.ndarray:
     ri = np.ascontiguousarray(ri, dtype=np.int64)
     out = np.empty(len(zi), dtype=np.float64)
     lib().oracle_power_points(_p(A), len(A), _p(T), K, M, _p(zi), _p(ri), len(zi), _p(out))
+    return out
+
+
+def interbin_points(A, T, zi, ci) -> np.ndarray:
+    """Interbinned plane ([K][2N] layout) at sampled (zi[p], column ci[p])."""
+    A, T = _c128(A), _c128(T)
+    K, M = T.shape
+    zi = np.ascontiguousarray(zi, dtype=np.int32)
+    ci = np.ascontiguousarray(ci, dtype=np.int64)
+    out = np.empty(len(zi), dtype=np.float64)
+    lib().oracle_interbin_points(_p(A), len(A), _p(T), K, M, _p(zi), _p(ci), len(zi), _p(out))
     return out
 
 
