@@ -145,6 +145,26 @@ int fdas_correlate_ex(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf32 *ban
                       int K, int M, int L, float *plane_dev, int grid,
                       hipStream_t stream);
 
+/*
+ * Forward correlation with interbinning (Sec. 3, eq. f-interp and the
+ * paragraph after it, which the paper's GPU code applies after the
+ * correlation): the Fourier amplitude midway between bins r and r+1 is
+ * estimated as (pi/4)(Y[z][r] - Y[z][r+1]).  Output plane2_dev has 2N
+ * floats per row, [K][2N] row-major:
+ *     plane2[z][2r]   = |Y[z][r]|^2,
+ *     plane2[z][2r+1] = |(pi/4)(Y[z][r] - Y[z][r+1])|^2,
+ * where Y[z][N] is the same correlation sum one bin past the end (the
+ * spectrum is zero outside [0, N)).  Arguments and errors as
+ * fdas_correlate; plane2_dev holds K*2N floats, 4-byte aligned.
+ */
+int fdas_correlate_interbin(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf32 *bank_dev,
+                            int K, int M, int L, float *plane2_dev, hipStream_t stream);
+
+/* Same with an explicit number of persistent workgroups (0 = resident). */
+int fdas_correlate_interbin_ex(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf32 *bank_dev,
+                               int K, int M, int L, float *plane2_dev, int grid,
+                               hipStream_t stream);
+
 /* Bytes of device workspace fdas_correlate_batched needs for nspec spectra
  * (the per-spectrum segment prefix sums), rounded up to 256. */
 size_t fdas_batched_workspace_bytes(int nspec);

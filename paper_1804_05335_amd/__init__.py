@@ -13,7 +13,8 @@ from __future__ import annotations
 from ._lib import (FdasError, fdas_backward_workspace_bytes, fdas_bank_elems,  # noqa: F401
                    fdas_batched_workspace_bytes, fdas_correlate, fdas_correlate_backward,
                    fdas_correlate_backward_ex, fdas_correlate_batched,
-                   fdas_correlate_batched_ex, fdas_correlate_ex, fdas_make_templates,
+                   fdas_correlate_batched_ex, fdas_correlate_ex, fdas_correlate_interbin,
+                   fdas_correlate_interbin_ex, fdas_make_templates,
                    fdas_make_templates_host, fdas_num_templates, fdas_prepare_bank,
                    fdas_template_response, fdas_version, lib)
 
@@ -46,6 +47,17 @@ def correlate(spec, bank, K: int, M: int, L: int, plane=None, grid: int = 0):
         plane = torch.empty((K, N), dtype=torch.float32, device=spec.device)
     fdas_correlate_ex(spec, N, bank, K, M, L, plane, grid)
     return plane
+
+
+def correlate_interbin(spec, bank, K: int, M: int, L: int, plane2=None, grid: int = 0):
+    """Interbinned plane [K][2N] (Sec. 3, eq. f-interp): even columns the bin
+    powers, odd columns the half-bin estimates |(pi/4)(Y_r - Y_r+1)|^2."""
+    import torch
+    N = spec.numel()
+    if plane2 is None:
+        plane2 = torch.empty((K, 2 * N), dtype=torch.float32, device=spec.device)
+    fdas_correlate_interbin_ex(spec, N, bank, K, M, L, plane2, grid)
+    return plane2
 
 
 def pack(spectra, device="cuda"):

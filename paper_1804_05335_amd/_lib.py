@@ -38,6 +38,8 @@ SIGNATURES = [
     ("fdas_make_templates", _I, [_D, _D, _I, _I, _P, _P, _P]),
     ("fdas_correlate", _I, [_P, _I64, _P, _I, _I, _I, _P, _P]),
     ("fdas_correlate_ex", _I, [_P, _I64, _P, _I, _I, _I, _P, _I, _P]),
+    ("fdas_correlate_interbin", _I, [_P, _I64, _P, _I, _I, _I, _P, _P]),
+    ("fdas_correlate_interbin_ex", _I, [_P, _I64, _P, _I, _I, _I, _P, _I, _P]),
     ("fdas_batched_workspace_bytes", _SZ, [_I]),
     ("fdas_correlate_batched", _I, [_P, _P, _I, _P, _I, _I, _I, _P, _P, _SZ, _P]),
     ("fdas_correlate_batched_ex", _I, [_P, _P, _I, _P, _I, _I, _I, _P, _I, _P, _SZ, _P]),
@@ -177,6 +179,22 @@ def fdas_correlate_ex(spec, N: int, bank, K: int, M: int, L: int, plane, grid: i
     _require(plane, torch.float32, "plane", K * N)
     _check(lib().fdas_correlate_ex(_ptr(spec), N, _ptr(bank), K, M, L, _ptr(plane), grid,
                                    _stream(stream, spec)), "fdas_correlate_ex")
+
+
+def fdas_correlate_interbin(spec, N: int, bank, K: int, M: int, L: int, plane2,
+                            stream=None) -> None:
+    fdas_correlate_interbin_ex(spec, N, bank, K, M, L, plane2, 0, stream)
+
+
+def fdas_correlate_interbin_ex(spec, N: int, bank, K: int, M: int, L: int, plane2, grid: int,
+                               stream=None) -> None:
+    import torch
+    _require(spec, torch.complex64, "spec", N)
+    _require(bank, torch.complex64, "bank", fdas_bank_elems(K, L))
+    _require(plane2, torch.float32, "plane2", 2 * K * N)
+    _check(lib().fdas_correlate_interbin_ex(_ptr(spec), N, _ptr(bank), K, M, L, _ptr(plane2),
+                                            grid, _stream(stream, spec)),
+           "fdas_correlate_interbin")
 
 
 def fdas_batched_workspace_bytes(nspec: int) -> int:

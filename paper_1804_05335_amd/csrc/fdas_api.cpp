@@ -208,8 +208,12 @@ int fdas_make_templates(double zmax, double dz, int M, int L, fdas_cf32* taps_de
     return ok();
 }
 
-int fdas_correlate_ex(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* bank_dev, int K,
-                      int M, int L, float* plane_dev, int grid, hipStream_t stream)
+}  // extern "C"
+
+namespace {
+
+int correlate_impl(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* bank_dev, int K, int M,
+                   int L, float* plane_dev, int grid, bool interbin, hipStream_t stream)
 {
     int st = check_geometry(K, M, L);
     if (st)
@@ -226,16 +230,39 @@ int fdas_correlate_ex(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* ban
         return fail(FDAS_INVALID_ARG, "misaligned pointer (spec 8 B, bank 16 B, plane 4 B)");
     hipError_t e = fdas::launch_forward(reinterpret_cast<const float2*>(spec_dev), N,
                                         reinterpret_cast<const float2*>(bank_dev), K, M, L,
-                                        plane_dev, grid, stream);
+                                        plane_dev, grid, interbin, stream);
     if (e != hipSuccess)
         return hip_fail(e, "forward launch");
     return ok();
 }
 
+}  // namespace
+
+extern "C" {
+
+int fdas_correlate_ex(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* bank_dev, int K,
+                      int M, int L, float* plane_dev, int grid, hipStream_t stream)
+{
+    return correlate_impl(spec_dev, N, bank_dev, K, M, L, plane_dev, grid, false, stream);
+}
+
 int fdas_correlate(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* bank_dev, int K, int M,
                    int L, float* plane_dev, hipStream_t stream)
 {
-    return fdas_correlate_ex(spec_dev, N, bank_dev, K, M, L, plane_dev, 0, stream);
+    return correlate_impl(spec_dev, N, bank_dev, K, M, L, plane_dev, 0, false, stream);
+}
+
+int fdas_correlate_interbin_ex(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* bank_dev,
+                               int K, int M, int L, float* plane2_dev, int grid,
+                               hipStream_t stream)
+{
+    return correlate_impl(spec_dev, N, bank_dev, K, M, L, plane2_dev, grid, true, stream);
+}
+
+int fdas_correlate_interbin(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* bank_dev,
+                            int K, int M, int L, float* plane2_dev, hipStream_t stream)
+{
+    return correlate_impl(spec_dev, N, bank_dev, K, M, L, plane2_dev, 0, true, stream);
 }
 
 size_t fdas_batched_workspace_bytes(int nspec)

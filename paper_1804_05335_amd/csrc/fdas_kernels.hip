@@ -109,6 +109,13 @@ struct Fwd {
     // next segment) is loaded into H as soon as the first inverse pass has
     // consumed it, so the load overlaps the rest of the transform without a
     // second register buffer.
+    //
+    // IB (interbinning, Sec. 3 eq. f-interp): the plane has 2N columns per
+    // row; column 2r holds |y_r|^2 and column 2r+1 |(pi/4)(y_r - y_{r+1})|^2.
+    // y is staged through the LDS ping-pong buffer so each lane can read its
+    // right-hand neighbour; the segment's spare valid output supplies y_{r+1}
+    // for its last output.
+    template <bool IB>
     __device__ static void item(const float2* __restrict__ spec, int64_t N,
                                 const float2* __restrict__ bank, int K, int M, int64_t s, int z0,
                                 int z1, float* __restrict__ plane, const float2 (&tw)[NTW],
@@ -125,13 +132,42 @@ struct Fwd {
             const int znext = z + 1 == K ? 0 : z + 1;
             auto next = [&]() { load_row(H, bank, znext, t); };
             F::template run_mul_hook<true, kMul>(X, H, v, la, lb, tw, t, next);
-            float* row = plane + (int64_t)z * N + out0;
+            if constexpr (!IB) {
+                float* row = plane + (int64_t)z * N + out0;
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int u = t + T * m - M / 2;
-                if (u >= 0 && u < B && out0 + u < N) {
-                    const float p = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
-                    __builtin_nontemporal_store(p, row + (unsigned)u);
+                for (int m = 0; m < E; ++m) {
+                    const int u = t + T * m - M / 2;
+                    if (u >= 0 && u < B && out0 + u < N) {
+                        const float p = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
+                        __builtin_nontemporal_store(p, row + (unsigned)u);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < E; ++m)
+                    la[lds_pad(t + T * m)] = v[m];
+                __syncthreads();
+                float2 nb[E];
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int q = t + T * m + 1;
+                    nb[m] = la[lds_pad(q < L ? q : L - 1)];
+                }
+                float2* tmp = la;
+                la = lb;
+                lb = tmp;
+                constexpr float kQ2 = 0.61685027506808491368f;   // (pi/4)^2
+                float* row = plane + 2 * ((int64_t)z * N + out0);
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int u = t + T * m - M / 2;
+                    if (u >= 0 && u < B && out0 + u < N) {
+                        const float p = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
+                        const float dx = v[m].x - nb[m].x, dy = v[m].y - nb[m].y;
+                        const float h = kQ2 * fmaf(dx, dx, dy * dy);
+                        __builtin_nontemporal_store(p, row + 2 * (unsigned)u);
+                        __builtin_nontemporal_store(h, row + 2 * (unsigned)u + 1);
+                    }
                 }
             }
         }
@@ -149,8 +185,9 @@ __device__ __forceinline__ void item_range(int64_t total, int64_t& i0, int64_t& 
     i1 = total * (w + 1) / P;
 }
 
-// One spectrum of N bins in nseg segments; persistent grid.
-template <int L>
+// One spectrum of N bins in nseg segments; persistent grid.  IB selects the
+// interbinned plane ([K][2N]) instead of the plain one ([K][N]).
+template <int L, bool IB>
 __global__ __launch_bounds__(Fwd<L>::T, 2) void forward_kernel(
     const float2* __restrict__ spec, int64_t N, const float2* __restrict__ bank, int K, int M,
     int64_t nseg, float* __restrict__ plane)
@@ -172,7 +209,7 @@ __global__ __launch_bounds__(Fwd<L>::T, 2) void forward_kernel(
         const int64_t s = i / K;
         const int zs = (int)(i - s * K);
         const int ze = (int)min<int64_t>(K, zs + (i1 - i));
-        W::item(spec, N, bank, K, M, s, zs, ze, plane, tw, la, lb, t, H);
+        W::template item<IB>(spec, N, bank, K, M, s, zs, ze, plane, tw, la, lb, t, H);
         i += ze - zs;
     }
 }
@@ -257,7 +294,7 @@ __global__ __launch_bounds__(Fwd<L>::T, 2) void batched_kernel(
         }
         const int64_t off = offsets[lo];
         const int64_t Nb = offsets[lo + 1] - off;
-        W::item(specs + off, Nb, bank, K, M, tile - segpre[lo], zs, ze,
+        W::template item<false>(specs + off, Nb, bank, K, M, tile - segpre[lo], zs, ze,
                 planes + (int64_t)K * off, tw, la, lb, t, H);
         i += ze - zs;
     }
@@ -463,36 +500,44 @@ static hipError_t resident_grid(Kern kernel, int threads, std::atomic<int>* cach
     return hipSuccess;
 }
 
-template <int L>
+template <int L, bool IB>
 static hipError_t launch_forward_L(const float2* spec, int64_t N, const float2* bank, int K,
                                    int M, float* plane, int grid, hipStream_t s)
 {
     static std::atomic<int> cache[64];
     const int64_t nseg = (N + (L - M) - 1) / (L - M);
     if (grid <= 0) {
-        hipError_t e = resident_grid(forward_kernel<L>, Fwd<L>::T, cache, &grid);
+        hipError_t e = resident_grid(forward_kernel<L, IB>, Fwd<L>::T, cache, &grid);
         if (e != hipSuccess)
             return e;
     }
     if ((int64_t)grid > nseg * K)
         grid = (int)(nseg * K);
-    hipLaunchKernelGGL(forward_kernel<L>, dim3(grid), dim3(Fwd<L>::T), 0, s, spec, N, bank, K,
-                       M, nseg, plane);
+    hipLaunchKernelGGL((forward_kernel<L, IB>), dim3(grid), dim3(Fwd<L>::T), 0, s, spec, N,
+                       bank, K, M, nseg, plane);
     return hipGetLastError();
 }
 
-hipError_t launch_forward(const float2* spec, int64_t N, const float2* bank, int K, int M,
-                          int L, float* plane, int grid, hipStream_t s)
+template <bool IB>
+static hipError_t launch_forward_ib(const float2* spec, int64_t N, const float2* bank, int K,
+                                    int M, int L, float* plane, int grid, hipStream_t s)
 {
     switch (L) {
-    case 256:  return launch_forward_L<256>(spec, N, bank, K, M, plane, grid, s);
-    case 512:  return launch_forward_L<512>(spec, N, bank, K, M, plane, grid, s);
-    case 1024: return launch_forward_L<1024>(spec, N, bank, K, M, plane, grid, s);
-    case 2048: return launch_forward_L<2048>(spec, N, bank, K, M, plane, grid, s);
-    case 4096: return launch_forward_L<4096>(spec, N, bank, K, M, plane, grid, s);
-    case 8192: return launch_forward_L<8192>(spec, N, bank, K, M, plane, grid, s);
+    case 256:  return launch_forward_L<256, IB>(spec, N, bank, K, M, plane, grid, s);
+    case 512:  return launch_forward_L<512, IB>(spec, N, bank, K, M, plane, grid, s);
+    case 1024: return launch_forward_L<1024, IB>(spec, N, bank, K, M, plane, grid, s);
+    case 2048: return launch_forward_L<2048, IB>(spec, N, bank, K, M, plane, grid, s);
+    case 4096: return launch_forward_L<4096, IB>(spec, N, bank, K, M, plane, grid, s);
+    case 8192: return launch_forward_L<8192, IB>(spec, N, bank, K, M, plane, grid, s);
     default:   return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_forward(const float2* spec, int64_t N, const float2* bank, int K, int M,
+                          int L, float* plane, int grid, bool interbin, hipStream_t s)
+{
+    return interbin ? launch_forward_ib<true>(spec, N, bank, K, M, L, plane, grid, s)
+                    : launch_forward_ib<false>(spec, N, bank, K, M, L, plane, grid, s);
 }
 
 template <int L>

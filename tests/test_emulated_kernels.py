@@ -121,3 +121,17 @@ def test_emulated_backward_vs_oracle(emu, L, M, N):
     rA, rT = native.grads(A, taps, w)
     assert _rel(gA, rA) < TOL
     assert _rel(gT, rT) < TOL
+
+
+@pytest.mark.parametrize("L,M,N,grid", [(256, 32, 1000, 0), (512, 64, 449, 3), (2048, 256, 1793, 0),
+                                        (256, 2, 37, 0)])
+def test_emulated_interbin_vs_oracle(emu, L, M, N, grid):
+    from oracle import direct
+    K = 3
+    A = syn.random_spectrum(7 * L + N, N)
+    taps = syn.random_taps(M + 2 * K, K, M)
+    bank = _bank(emu, taps, L)
+    plane2 = np.full((K, 2 * N), np.nan, dtype=np.float32)
+    assert emu.fdas_correlate_interbin_ex(_p(A), ctypes.c_int64(N), _p(bank), K, M, L,
+                                          _p(plane2), grid, None) == 0
+    assert _rel(plane2, direct.interbinned_power(A, taps)) < TOL
