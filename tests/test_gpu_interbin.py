@@ -41,9 +41,12 @@ def test_interbin_full_plane_workload1(fd, w1, L):
     assert _rel(P2, ref) < TOL
     plain = fd.correlate(spec, bank, w1.K, w1.M, L).cpu().numpy()
     assert np.array_equal(P2[:, 0::2], plain)
-    # the injected signal sits at r0 = 20000.3: the bin beats the half-bin
+    # the injected signal sits at r0 = 20000.3, z0 = +8: the peak is at z0
+    # and the oracle's value there is its maximum (the half-bin 20000.5 is
+    # nearer than bin 20000, so column 40001 wins)
     zz, cc = np.unravel_index(np.argmax(P2), P2.shape)
-    assert ot.z_grid(w1.zmax, w1.dz)[zz] == 8.0 and cc == 40000
+    assert ot.z_grid(w1.zmax, w1.dz)[zz] == 8.0 and cc in (40000, 40001)
+    assert ref[zz, cc] >= ref.max() * (1 - 2 * TOL)
 
 
 @pytest.mark.parametrize("N", [1, 2, 447, 448, 449, 5000])
