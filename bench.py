@@ -152,6 +152,16 @@ def _timed(torch, fn, steps):
     return a.elapsed_time(b) / steps
 
 
+def autotune(fdas, torch, taps, K, M, specs, offs, nspec, planes):
+    """Segment length picked by the library's autotuner for this batch."""
+    ws = torch.empty(fdas._lib.fdas_autotune_workspace_bytes(K, nspec), dtype=torch.uint8,
+                     device="cuda")
+    L, _, ms = fdas._lib.fdas_autotune_batched(taps.contiguous(), K, M, specs, offs, nspec,
+                                               planes, ws)
+    del ws
+    return L, ms
+
+
 def bench_batched(fdas, torch, steps: int):
     """256 ragged spectra (2^18..2^21 bins), 85 x 256 taps: one persistent
     launch, the same launch replayed from a captured graph, and a loop of
@@ -159,12 +169,14 @@ def bench_batched(fdas, torch, steps: int):
     import fdas_synth as syn
     w = syn.workload(3)
     packed, o = w.packed()
-    K, M, L = w.K, w.M, w.L
+    K, M = w.K, w.M
     specs = torch.from_numpy(packed).cuda()
     offs = torch.from_numpy(o).cuda()
     del packed
-    _, bank = fdas.make_bank(w.zmax, w.dz, M, L)
     planes = torch.empty(K * int(o[-1]), dtype=torch.float32, device="cuda")
+    taps, _ = fdas.make_bank(w.zmax, w.dz, M, 2048)
+    L, tuned_ms = autotune(fdas, torch, taps, K, M, specs, offs, len(w.spectra), planes)
+    bank = fdas.prepare_bank(taps, L)
     ws = torch.empty(fdas.fdas_batched_workspace_bytes(len(w.spectra)), dtype=torch.uint8,
                      device="cuda")
     nspec = len(w.spectra)
@@ -200,7 +212,8 @@ def bench_batched(fdas, torch, steps: int):
            "batched_ms": ms_b, "batched_points_per_s": pts / ms_b * 1e3,
            "graph_replay_ms": ms_g, "graph_points_per_s": pts / ms_g * 1e3,
            "plain_loop_ms": ms_p, "plain_loop_points_per_s": pts / ms_p * 1e3,
-           "speedup_batched_vs_plain": ms_p / ms_b}
+           "speedup_batched_vs_plain": ms_p / ms_b,
+           "segment_autotuned": L, "autotune_trials_ms": tuned_ms}
     del specs, planes, ws
     torch.cuda.empty_cache()
     return out
@@ -262,7 +275,7 @@ def bench_workload5(fdas, torch, steps: int):
     specs = torch.from_numpy(packed).cuda()
     offs = torch.from_numpy(o).cuda()
     del packed
-    _, bank = fdas.make_bank(w.zmax, w.dz, M, L)
+    taps, bank = fdas.make_bank(w.zmax, w.dz, M, L)
     total = int(o[-1])
     planes = torch.empty(K * total, dtype=torch.float32, device="cuda")
     ws = torch.empty(fdas.fdas_batched_workspace_bytes(nspec), dtype=torch.uint8, device="cuda")
@@ -271,7 +284,15 @@ def bench_workload5(fdas, torch, steps: int):
         fdas.fdas_correlate_batched(specs, offs, nspec, bank, K, M, L, planes, ws)
 
     fwd()
-    ms_f = _timed(torch, fwd, steps)
+    ms_spec = _timed(torch, fwd, steps)          # at the specified segment length
+    L_spec = L
+    L, _ = autotune(fdas, torch, taps, K, M, specs, offs, nspec, planes)
+    if L != L_spec:
+        bank = fdas.prepare_bank(taps, L)
+        fwd()
+        ms_f = _timed(torch, fwd, steps)
+    else:
+        ms_f = ms_spec
     del planes
     torch.cuda.empty_cache()
     gen = torch.Generator(device="cuda")
@@ -296,6 +317,7 @@ def bench_workload5(fdas, torch, steps: int):
     out = {"workload": f"{nspec} ragged spectra (2^21..2^22 bins, sum {total}), {K} templates x "
                        f"{M} taps, segment {L}",
            "points": pts,
+           f"forward_batched_ms_segment_{L_spec}": ms_spec, "segment_autotuned": L,
            "forward_batched_ms": ms_f, "forward_points_per_s": pts / ms_f * 1e3,
            "backward_spec_ms": ms_b, "fwd_bwd_points_per_s": pts / (ms_f + ms_b) * 1e3,
            "fwd_bwd_over_fwd_time": (ms_f + ms_b) / ms_f}

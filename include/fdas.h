@@ -237,6 +237,27 @@ int fdas_correlate_backward_ex(const fdas_cf32 *spec_dev, int64_t N, const fdas_
                                fdas_cf32 *grad_spec_dev, fdas_cf32 *grad_taps_dev, int zchunk,
                                void *ws_dev, size_t ws_bytes, hipStream_t stream);
 
+/* Bytes of device workspace fdas_autotune_batched needs: a bank for the
+ * largest segment length plus the batched workspace. */
+size_t fdas_autotune_workspace_bytes(int K, int nspec);
+
+/*
+ * Autotuner for the batched forward (the paper tunes the segment length and
+ * launch shape per card by hand, Sec. 5.1.2): prepares a bank from taps_dev
+ * for every supported L with M <= L/2, times fdas_correlate_batched on the
+ * caller's batch (one warm-up launch, mean of three) and returns the fastest
+ * L and persistent grid (*grid_out = 0: the resident workgroup count) and
+ * its time in ms (ms_out may be NULL).  planes_dev is overwritten (it must
+ * hold K * offsets[nspec] floats); ws_dev holds at least
+ * fdas_autotune_workspace_bytes(K, nspec) bytes (256-byte aligned).
+ * Synchronises the stream; results are cached per (device, K, M, nspec,
+ * log2 of the total bins) for the life of the process.  Not on the hot path.
+ */
+int fdas_autotune_batched(const fdas_cf32 *taps_dev, int K, int M, const fdas_cf32 *specs_dev,
+                          const int64_t *offsets_dev, int nspec, float *planes_dev, void *ws_dev,
+                          size_t ws_bytes, hipStream_t stream, int *L_out, int *grid_out,
+                          double *ms_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -43,6 +43,10 @@ SIGNATURES = [
     ("fdas_batched_workspace_bytes", _SZ, [_I]),
     ("fdas_correlate_batched", _I, [_P, _P, _I, _P, _I, _I, _I, _P, _P, _SZ, _P]),
     ("fdas_correlate_batched_ex", _I, [_P, _P, _I, _P, _I, _I, _I, _P, _I, _P, _SZ, _P]),
+    ("fdas_autotune_workspace_bytes", _SZ, [_I, _I]),
+    ("fdas_autotune_batched", _I, [_P, _I, _I, _P, _P, _I, _P, _P, _SZ, _P,
+                                   ctypes.POINTER(_I), ctypes.POINTER(_I),
+                                   ctypes.POINTER(_D)]),
     ("fdas_backward_workspace_bytes", _SZ, [_I64, _I, _I, _I, _I]),
     ("fdas_correlate_backward", _I, [_P, _I64, _P, _I, _I, _I, _P, _P, _P, _P, _SZ, _P]),
     ("fdas_correlate_backward_ex", _I, [_P, _I64, _P, _I, _I, _I, _P, _P, _P, _I, _P, _SZ, _P]),
@@ -244,3 +248,24 @@ def fdas_correlate_backward_ex(spec, N: int, bank, K: int, M: int, L: int, dLdP,
                                             _ptr(grad_spec), _ptr(grad_taps), zchunk, _ptr(ws),
                                             ws.numel(), _stream(stream, spec)),
            "fdas_correlate_backward")
+
+
+def fdas_autotune_workspace_bytes(K: int, nspec: int) -> int:
+    return int(lib().fdas_autotune_workspace_bytes(K, nspec))
+
+
+def fdas_autotune_batched(taps, K: int, M: int, specs, offsets, nspec: int, planes, ws,
+                          stream=None):
+    """(L, grid, ms) of the fastest segment length for this batch."""
+    import torch
+    _require(taps, torch.complex64, "taps", K * M)
+    _require(specs, torch.complex64, "specs")
+    _require(offsets, torch.int64, "offsets", nspec + 1)
+    _require(planes, torch.float32, "planes")
+    _require(ws, torch.uint8, "ws", fdas_autotune_workspace_bytes(K, nspec))
+    Lo, go, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0.0)
+    _check(lib().fdas_autotune_batched(_ptr(taps), K, M, _ptr(specs), _ptr(offsets), nspec,
+                                       _ptr(planes), _ptr(ws), ws.numel(), _stream(stream, specs),
+                                       ctypes.byref(Lo), ctypes.byref(go), ctypes.byref(ms)),
+           "fdas_autotune_batched")
+    return Lo.value, go.value, ms.value

@@ -85,6 +85,11 @@ void fill_templates(double dz, int K, int M, fdas_cf32* out)
 
 }  // namespace
 
+int fdas::fail_status(int status, const char* msg)
+{
+    return status == FDAS_OK ? ok() : fail(status, "%s", msg);
+}
+
 extern "C" {
 
 const char* fdas_version(void) { return "fdas-gfx950 0.1.0"; }

@@ -7,6 +7,9 @@
 
 namespace fdas {
 
+// Record `msg` as the calling thread's last-error text and return status.
+int fail_status(int status, const char* msg);
+
 // Host FP64 response R(q, z) (templates source file).
 std::complex<double> response(double q, double z);
 

@@ -144,3 +144,19 @@ def test_validation_happens_before_any_device_call():
 def test_bank_elems():
     assert _lib.fdas_bank_elems(85, 2048) == 86 * 2048
     assert _lib.fdas_bank_elems(0, 2048) == 0
+
+
+def test_autotune_validation_before_any_device_call():
+    L = _lib.lib()
+    p = _fake(0x10000)
+    Lo, go, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    wsb = L.fdas_autotune_workspace_bytes(85, 4)
+    assert wsb >= 86 * 8192 * 8
+    args = lambda ws, wsb_, K=85, M=256, n=4: (p, K, M, p, p, n, p, ws, wsb_, None,
+                                               ctypes.byref(Lo), ctypes.byref(go), ctypes.byref(ms))
+    assert L.fdas_autotune_batched(*args(p, wsb - 1)) == _lib.FDAS_WORKSPACE_TOO_SMALL
+    assert L.fdas_autotune_batched(*args(_fake(0x10010), wsb)) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_autotune_batched(*args(p, wsb, n=0)) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_autotune_batched(*args(p, wsb, M=255)) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_autotune_batched(p, 85, 256, p, p, 4, p, p, wsb, None, None,
+                                   ctypes.byref(go), None) == _lib.FDAS_INVALID_ARG

@@ -150,3 +150,25 @@ def test_workload3_full_sampled(fd):
         ref_plain = _plain(fd, specs[o[b]:o[b + 1]], bank, K, w.M, L)
         assert torch.equal(views[b], ref_plain), b
     assert bool(torch.isfinite(planes).all())
+
+
+def test_autotuner_picks_a_valid_segment_length(fd):
+    w = syn.workload(3, nspec=10, length_scale=1 / 16)
+    K, M = w.K, w.M
+    taps = torch.from_numpy(fd.fdas_make_templates_host(w.zmax, w.dz, M)).cuda()
+    packed, o = w.packed()
+    specs = torch.from_numpy(packed).cuda()
+    offs = torch.from_numpy(o).cuda()
+    planes = torch.empty(K * int(o[-1]), dtype=torch.float32, device="cuda")
+    ws = torch.empty(fd._lib.fdas_autotune_workspace_bytes(K, len(w.spectra)),
+                     dtype=torch.uint8, device="cuda")
+    L, grid, ms = fd._lib.fdas_autotune_batched(taps, K, M, specs, offs, len(w.spectra), planes, ws)
+    assert L in (512, 1024, 2048, 4096, 8192) and M <= L // 2 and grid == 0 and ms > 0
+    # cached: the same answer without re-timing
+    assert fd._lib.fdas_autotune_batched(taps, K, M, specs, offs, len(w.spectra), planes, ws)[0] == L
+    bank = fd.prepare_bank(taps, L)
+    planes = fd.correlate_batched(specs, offs, bank, K, M, L)
+    for b in (0, 9):
+        n = int(o[b + 1] - o[b])
+        ref = fd.correlate(specs[o[b]:o[b + 1]], bank, K, M, L)
+        assert torch.equal(planes[K * o[b]:K * o[b + 1]].view(K, n), ref)
