@@ -3,7 +3,11 @@
 Every source is compiled for gfx950 only, with packed-FP32 instruction
 selection disabled (``-packed-fp32-ops``): the compiler would otherwise
 form v_pk_*_f32 from ordinary float code, and those are kept out of this
-library.  Run ``python -m paper_1804_05335_amd.build`` or call ``build()``.
+library.  Implicit FMA contraction is off (``-ffp-contract=off``): the
+kernels spell out every fused multiply-add, so each instantiation of the
+shared FFT code rounds identically (the plain, batched and interbinned
+planes agree bit for bit).  Run ``python -m paper_1804_05335_amd.build`` or
+call ``build()``.
 """
 from __future__ import annotations
 
@@ -20,7 +24,7 @@ LIB = os.path.join(HERE, "libfdas.so")
 SOURCES = ["fdas_api.cpp", "fdas_templates.cpp", "fdas_tune.cpp", "fdas_kernels.hip"]
 
 ARCH = "gfx950"
-COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
+COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-ffp-contract=off",
           "-I", os.path.join(ROOT, "include"),
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

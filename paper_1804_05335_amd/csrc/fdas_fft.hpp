@@ -47,30 +47,38 @@ __device__ __forceinline__ float2 rot4(float2 a)
     return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
 }
 
-template <bool INV>
-__device__ __forceinline__ float2 twiddle(float2 a, float2 w)
-{
-    return INV ? cmulc(a, w) : cmul(a, w);
-}
-
 constexpr float kSqrtHalf = 0.70710678118654752440f;
 constexpr float kCos8 = 0.92387953251128675613f;   // cos(pi/8)
 constexpr float kSin8 = 0.38268343236508977173f;   // sin(pi/8)
 
-// a * W8^1 (forward W8 = exp(-i pi/4); inverse uses the conjugate)
+// The eighth roots of unity W8^1 and W8^3 are sqrt(1/2) times a vector whose
+// components are a sum and a difference of the input's.  r81/r83 return that
+// unscaled vector, so the scale can be fused into the following additions:
+// e +- y W8^k = fma(+-r, sqrt(1/2), e).  The inverse transform uses the
+// conjugate roots.
 template <bool INV>
-__device__ __forceinline__ float2 rot8_1(float2 a)
+__device__ __forceinline__ float2 r81(float2 a)
 {
-    return INV ? make_float2((a.x - a.y) * kSqrtHalf, (a.x + a.y) * kSqrtHalf)
-               : make_float2((a.x + a.y) * kSqrtHalf, (a.y - a.x) * kSqrtHalf);
+    return INV ? make_float2(a.x - a.y, a.x + a.y) : make_float2(a.x + a.y, a.y - a.x);
+}
+template <bool INV>
+__device__ __forceinline__ float2 r83(float2 a)
+{
+    return INV ? make_float2(-(a.x + a.y), a.x - a.y) : make_float2(a.y - a.x, -(a.x + a.y));
 }
 
-// a * W8^3
-template <bool INV>
-__device__ __forceinline__ float2 rot8_3(float2 a)
+// e + k r and e - k r, two FMAs per component.
+__device__ __forceinline__ void fbfly(float2& hi, float2& lo, float2 e, float2 r, float k)
 {
-    return INV ? make_float2(-(a.x + a.y) * kSqrtHalf, (a.x - a.y) * kSqrtHalf)
-               : make_float2((a.y - a.x) * kSqrtHalf, -(a.x + a.y) * kSqrtHalf);
+    hi = make_float2(fmaf(r.x, k, e.x), fmaf(r.y, k, e.y));
+    lo = make_float2(fmaf(-r.x, k, e.x), fmaf(-r.y, k, e.y));
+}
+
+// a + b and a - b
+__device__ __forceinline__ void bfly(float2& hi, float2& lo, float2 a, float2 b)
+{
+    hi = cadd(a, b);
+    lo = csub(a, b);
 }
 
 // ---- radix-R DFT codelets, natural order in and out ----------------------
@@ -123,25 +131,26 @@ __device__ __forceinline__ void stage1(float2 (&x)[R], const float2 (&w)[R])
     }
 }
 
-// Remaining stages, given stage1 has run.
+// Remaining stages, given stage1 has run.  All arithmetic is spelled out
+// (the library is built without implicit FMA contraction, so every
+// instantiation rounds identically).
 template <bool INV>
 __device__ __forceinline__ void rest4(float2& x0, float2& x1, float2& x2, float2& x3)
 {
     // after stage 1: x0 = t0, x2 = t1, x1 = t2, x3 = t3' (pairs (0,2), (1,3))
     const float2 t0 = x0, t1 = x2, t2 = x1, t3 = rot4<INV>(x3);
-    x0 = cadd(t0, t2);
-    x2 = csub(t0, t2);
-    x1 = cadd(t1, t3);
-    x3 = csub(t1, t3);
+    bfly(x0, x2, t0, t2);
+    bfly(x1, x3, t1, t3);
 }
 
+// DFT4 of (a0, a1, a2, a3) given s02 = a0 + a2, d02 = a0 - a2, s13 = a1 + a3,
+// d13 = a1 - a3: outputs X0..X3.
 template <bool INV>
-__device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2& x3)
+__device__ __forceinline__ void dft4_tail(float2& X0, float2& X1, float2& X2, float2& X3, float2 s02,
+                                          float2 d02, float2 s13, float2 d13)
 {
-    float2 a = x0, b = x2, c = x1, d = x3;
-    x0 = cadd(a, b); x2 = csub(a, b);
-    x1 = cadd(c, d); x3 = csub(c, d);
-    rest4<INV>(x0, x1, x2, x3);
+    bfly(X0, X2, s02, s13);
+    bfly(X1, X3, d02, rot4<INV>(d13));
 }
 
 template <int R, bool INV>
@@ -153,40 +162,58 @@ __device__ __forceinline__ void rest(float2 (&x)[R])
         rest4<INV>(x[0], x[1], x[2], x[3]);
     } else if constexpr (R == 8) {
         // evens e = (x0, x2, x4, x6), odds o = (x1, x3, x5, x7); stage 1 paired
-        // (0,4), (2,6), (1,5), (3,7), i.e. the first stage of both radix-4 DFTs
+        // (0,4), (2,6), (1,5), (3,7), i.e. the first stage of both radix-4 DFTs;
+        // then X[k] = E[k] + W8^k O[k], X[k+4] = E[k] - W8^k O[k]
         float2 e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
         float2 o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
         rest4<INV>(e0, e1, e2, e3);
         rest4<INV>(o0, o1, o2, o3);
-        o1 = rot8_1<INV>(o1);
-        o2 = rot4<INV>(o2);
-        o3 = rot8_3<INV>(o3);
-        x[0] = cadd(e0, o0); x[4] = csub(e0, o0);
-        x[1] = cadd(e1, o1); x[5] = csub(e1, o1);
-        x[2] = cadd(e2, o2); x[6] = csub(e2, o2);
-        x[3] = cadd(e3, o3); x[7] = csub(e3, o3);
+        bfly(x[0], x[4], e0, o0);
+        fbfly(x[1], x[5], e1, r81<INV>(o1), kSqrtHalf);
+        bfly(x[2], x[6], e2, rot4<INV>(o2));
+        fbfly(x[3], x[7], e3, r83<INV>(o3), kSqrtHalf);
     } else if constexpr (R == 16) {
         // 16 = 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2.  Stage 1 paired (n2, 8+n2)
         // and (4+n2, 12+n2): the first stage of each radix-4 DFT over n1.
 #pragma unroll
         for (int n2 = 0; n2 < 4; ++n2)
             rest4<INV>(x[n2], x[4 + n2], x[8 + n2], x[12 + n2]);
-        // x[4 k1 + n2] holds Y[n2][k1]; twiddle by W16^(n2 k1)
+        // x[4 k1 + n2] holds Y[n2][k1]; row k1 is a DFT4 over n2 of
+        // a_n2 = Y[n2][k1] W16^(n2 k1), with the twiddle fused into its first
+        // stage.  W16^2 = W8^1, W16^4 = rot4, W16^6 = W8^3, W16^9 = -W16^1.
         const float2 w1 = make_float2(kCos8, INV ? kSin8 : -kSin8);
         const float2 w3 = make_float2(kSin8, INV ? kCos8 : -kCos8);
         const float2 w9 = make_float2(-kCos8, INV ? -kSin8 : kSin8);
-        x[4 + 1] = cmul(x[4 + 1], w1);
-        x[4 + 2] = rot8_1<INV>(x[4 + 2]);
-        x[4 + 3] = cmul(x[4 + 3], w3);
-        x[8 + 1] = rot8_1<INV>(x[8 + 1]);
-        x[8 + 2] = rot4<INV>(x[8 + 2]);
-        x[8 + 3] = rot8_3<INV>(x[8 + 3]);
-        x[12 + 1] = cmul(x[12 + 1], w3);
-        x[12 + 2] = rot8_3<INV>(x[12 + 2]);
-        x[12 + 3] = cmul(x[12 + 3], w9);
-#pragma unroll
-        for (int k1 = 0; k1 < 4; ++k1)
-            dft4<INV>(x[4 * k1 + 0], x[4 * k1 + 1], x[4 * k1 + 2], x[4 * k1 + 3]);
+        float2 s02, d02, s13, d13;
+        // row 0: no twiddles
+        bfly(s02, d02, x[0], x[2]);
+        bfly(s13, d13, x[1], x[3]);
+        dft4_tail<INV>(x[0], x[1], x[2], x[3], s02, d02, s13, d13);
+        // row 1: (1, W1, W2, W3)
+        fbfly(s02, d02, x[4], r81<INV>(x[6]), kSqrtHalf);
+        {
+            const float2 a = cmul(x[5], w1);
+            s13 = add_mulw<kMul>(a, x[7], w3);
+            d13 = make_float2(fmaf(2.f, a.x, -s13.x), fmaf(2.f, a.y, -s13.y));
+        }
+        dft4_tail<INV>(x[4], x[5], x[6], x[7], s02, d02, s13, d13);
+        // row 2: (1, W2, W4, W6); W2 y1 +- W6 y3 = W8^1 (y1 +- rot4(y3))
+        bfly(s02, d02, x[8], rot4<INV>(x[10]));
+        {
+            float2 c, e;
+            bfly(c, e, x[9], rot4<INV>(x[11]));
+            const float2 pc = r81<INV>(c), pe = rot4<INV>(r81<INV>(e));
+            fbfly(x[8], x[10], s02, pc, kSqrtHalf);
+            fbfly(x[9], x[11], d02, pe, kSqrtHalf);
+        }
+        // row 3: (1, W3, W6, W9)
+        fbfly(s02, d02, x[12], r83<INV>(x[14]), kSqrtHalf);
+        {
+            const float2 a = cmul(x[13], w3);
+            s13 = add_mulw<kMul>(a, x[15], w9);
+            d13 = make_float2(fmaf(2.f, a.x, -s13.x), fmaf(2.f, a.y, -s13.y));
+        }
+        dft4_tail<INV>(x[12], x[13], x[14], x[15], s02, d02, s13, d13);
         // x[4 k1 + k2] holds X[k1 + 4 k2]; transpose the 4x4 index back
         float2 y[16];
 #pragma unroll
@@ -348,6 +375,13 @@ struct FFT<L, E, Radices<Rs...>> {
         NoHook none;
         run_passes<L, E, INV, kNoMul, 1, 0, NTW, NoHook, Rs...>(v, v, v, lds_a, lds_b, tw, t, none);
     }
+    // as run; hook() runs once the first pass has read v
+    template <bool INV, class Hook>
+    __device__ static void run_hook(float2 (&v)[E], float2*& lds_a, float2*& lds_b,
+                                    const float2 (&tw)[NTW], int t, Hook& hook)
+    {
+        run_passes<L, E, INV, kNoMul, 1, 0, NTW, Hook, Rs...>(v, v, v, lds_a, lds_b, tw, t, hook);
+    }
     // v = transform of in[m] * pre[m] (MODE kMul) or in[m] * conj(pre[m]) (kMulConj)
     template <bool INV, int MODE>
     __device__ static void run_mul(const float2 (&in)[E], const float2 (&pre)[E], float2 (&v)[E],
@@ -393,11 +427,20 @@ template <int L>
 struct Geometry {
     static constexpr int E = L <= 256 ? 4 : (L <= 512 ? 8 : FDAS_FWD_E);
 };
-// Values per lane of the adjoint, which keeps four transform-sized arrays
-// live: 8 from L = 512 on.
+// Values per lane of the adjoint, which keeps five transform-sized arrays
+// live (window, accumulator, work array, two bank rows): 8 from L = 512 on,
+// 16 at L = 8192 so a workgroup stays at 512 lanes.  kMinWaves is the
+// occupancy (waves per SIMD) the register allocation is held to.
+#ifndef FDAS_BWD_WAVES
+#define FDAS_BWD_WAVES 2
+#endif
+#ifndef FDAS_BWD_E8192
+#define FDAS_BWD_E8192 16
+#endif
 template <int L>
 struct BwdGeometry {
-    static constexpr int E = L <= 256 ? 4 : 8;
+    static constexpr int E = L <= 256 ? 4 : (L >= 8192 ? FDAS_BWD_E8192 : 8);
+    static constexpr int kMinWaves = L >= 8192 ? 1 : FDAS_BWD_WAVES;
 };
 
 }  // namespace fdas

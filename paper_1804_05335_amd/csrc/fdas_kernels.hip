@@ -11,6 +11,41 @@
 
 namespace fdas {
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+#ifndef FDAS_IB_GROUP
+#define FDAS_IB_GROUP 4
+#endif
+constexpr int kIbGroup = FDAS_IB_GROUP;
+
+// ---- range-checked segment access ---------------------------------------------
+//
+// A segment's window positions q in [0, L) map to output u = q - M/2; only
+// q in [M/2, M/2 + nvalid) are valid outputs (nvalid = min(B, N - out0)).
+// Per-element branches are replaced by buffer instructions whose resource
+// starts at position q = 0 of the row and ends after the last valid output:
+// the hardware drops stores past the end and returns 0 for loads past it,
+// and positions q < M/2 are given byte offset 2^31, which is past it as
+// well.  Offsets are built from non-negative terms only, so no wrap-around
+// is involved however the compiler splits them into register and immediate
+// parts.
+constexpr int kRsrcWord3 = 0x00020000;   // gfx9 raw buffer: 32-bit data format, no swizzle
+constexpr int kNonTemporal = 2;          // cache policy: non-temporal
+
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t seg_rsrc(const void* row_q0, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(row_q0), (short)0, bytes,
+                                             kRsrcWord3);
+}
+
+template <int BYTES>
+__device__ __forceinline__ int seg_off(int q, int half_m)
+{
+    return q >= half_m ? q * BYTES : (int)0x80000000u;
+}
+
 // ---- bank preparation (off the hot path) ------------------------------------
 //
 // H_z[k] = (1/L) sum_j conj(T[z][j]) W_L^{((M/2 - j) mod L) k}: tap j of the
@@ -123,6 +158,7 @@ struct Fwd {
     {
         const int B = L - M;
         const int64_t out0 = s * B;
+        const int nvalid = (int)min<int64_t>(B, N - out0);   // >= 1: segment s < nseg
         float2 X[E];
         load_window(X, spec, N, out0 - M / 2, t);
         F::template run<false>(X, la, lb, tw, t);
@@ -133,42 +169,48 @@ struct Fwd {
             auto next = [&]() { load_row(H, bank, znext, t); };
             F::template run_mul_hook<true, kMul>(X, H, v, la, lb, tw, t, next);
             if constexpr (!IB) {
-                float* row = plane + (int64_t)z * N + out0;
+                const float* row_q0 = plane + ((int64_t)z * N + out0 - M / 2);
+                const auto rs = seg_rsrc(row_q0, (M / 2 + nvalid) * 4);
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
-                    const int u = t + T * m - M / 2;
-                    if (u >= 0 && u < B && out0 + u < N) {
-                        const float p = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
-                        __builtin_nontemporal_store(p, row + (unsigned)u);
-                    }
+                    const float p = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(p), rs,
+                                                          seg_off<4>(t + T * m, M / 2), 0,
+                                                          kNonTemporal);
                 }
             } else {
 #pragma unroll
                 for (int m = 0; m < E; ++m)
                     la[lds_pad(t + T * m)] = v[m];
                 __syncthreads();
-                float2 nb[E];
+                // both y_r and y_{r+1} are read back from LDS so v is dead here;
+                // for valid outputs q + 1 <= M/2 + B = L - M/2 stays inside the
+                // segment (the clamp only serves positions whose store is dropped)
+                constexpr float kQ2 = 0.61685027506808491368f;   // (pi/4)^2
+                const float* row_q0 = plane + 2 * ((int64_t)z * N + out0 - M / 2);
+                const auto rs = seg_rsrc(row_q0, (M / 2 + nvalid) * 8);
+                // in groups of kIbGroup elements, each fenced off from the
+                // scheduler so the reads of later groups are not hoisted
+                // (which would raise the register peak and spill)
 #pragma unroll
-                for (int m = 0; m < E; ++m) {
-                    const int q = t + T * m + 1;
-                    nb[m] = la[lds_pad(q < L ? q : L - 1)];
+                for (int g = 0; g < E; g += kIbGroup) {
+#pragma unroll
+                    for (int m = g; m < g + kIbGroup; ++m) {
+                        const int q = t + T * m;
+                        const int qn = q + 1 < L ? q + 1 : L - 1;
+                        const float2 a = la[lds_pad(q)], b = la[lds_pad(qn)];
+                        const float p = fmaf(a.x, a.x, a.y * a.y);
+                        const float dx = a.x - b.x, dy = a.y - b.y;
+                        const float h = kQ2 * fmaf(dx, dx, dy * dy);
+                        const u32x2 ph = {__float_as_uint(p), __float_as_uint(h)};
+                        __builtin_amdgcn_raw_buffer_store_b64(ph, rs, seg_off<8>(q, M / 2), 0,
+                                                              kNonTemporal);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
                 }
                 float2* tmp = la;
                 la = lb;
                 lb = tmp;
-                constexpr float kQ2 = 0.61685027506808491368f;   // (pi/4)^2
-                float* row = plane + 2 * ((int64_t)z * N + out0);
-#pragma unroll
-                for (int m = 0; m < E; ++m) {
-                    const int u = t + T * m - M / 2;
-                    if (u >= 0 && u < B && out0 + u < N) {
-                        const float p = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
-                        const float dx = v[m].x - nb[m].x, dy = v[m].y - nb[m].y;
-                        const float h = kQ2 * fmaf(dx, dx, dy * dy);
-                        __builtin_nontemporal_store(p, row + 2 * (unsigned)u);
-                        __builtin_nontemporal_store(h, row + 2 * (unsigned)u + 1);
-                    }
-                }
             }
         }
     }
@@ -322,15 +364,21 @@ struct Bwd {
     static constexpr int T = W::T;
     static constexpr int NTW = W::NTW;
 
+    // Templates [z0, z1) of window s.  Hc holds bank row z0 on entry.  Per
+    // template the weights w_z are loaded before the inverse transform and
+    // the next bank row is loaded once the first pass of FFT(g) has started,
+    // so neither load's latency sits on the critical path; row z stays live
+    // for the accumulate step.
     __device__ static void item(const float2* __restrict__ spec, int64_t N,
                                 const float2* __restrict__ bank, int M, int64_t s, int z0,
                                 int z1, const float* __restrict__ dLdP, bool want_A,
                                 bool want_T, float2* __restrict__ partA,
                                 float2* __restrict__ partT, const float2 (&tw)[NTW],
-                                float2*& la, float2*& lb, int t)
+                                float2*& la, float2*& lb, int t, float2 (&Hc)[E])
     {
         const int B = L - M;
         const int64_t out0 = s * B;
+        const int nvalid = (int)min<int64_t>(B, N - out0);   // >= 1: window s < nwin
         float2 X[E];
         W::load_window(X, spec, N, out0 - M / 2, t);
         F::template run<false>(X, la, lb, tw, t);
@@ -341,29 +389,28 @@ struct Bwd {
             acc[m] = make_float2(0.f, 0.f);
 
         for (int z = z0; z < z1; ++z) {
-            float2 H[E];
-            W::load_row(H, bank, z, t);
-            float2 v[E];
-            F::template run_mul<true, kMul>(X, H, v, la, lb, tw, t);     // y = IFFT(X H_z)
-            // g = 2 w y on the owned outputs, zero elsewhere
-            const float* wz = dLdP + (int64_t)z * N + out0;
+            // 2 w on the owned outputs, zero elsewhere (w is read exactly once;
+            // out-of-range buffer loads return 0)
+            const auto rw = seg_rsrc(dLdP + ((int64_t)z * N + out0 - M / 2), (M / 2 + nvalid) * 4);
+            float wv[E];
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int u = t + T * m - M / 2;
-                float wv = 0.f;
-                if (u >= 0 && u < B && out0 + u < N)
-                    wv = 2.f * wz[(unsigned)u];
-                v[m] = make_float2(wv * v[m].x, wv * v[m].y);
-            }
-            F::template run<false>(v, la, lb, tw, t);                     // G = FFT(g)
+            for (int m = 0; m < E; ++m)
+                wv[m] = 2.f * __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                                  rw, seg_off<4>(t + T * m, M / 2), 0, kNonTemporal));
+            float2 v[E];
+            F::template run_mul<true, kMul>(X, Hc, v, la, lb, tw, t);     // y = IFFT(X H_z)
+#pragma unroll
+            for (int m = 0; m < E; ++m)                                   // g = 2 w y
+                v[m] = make_float2(wv[m] * v[m].x, wv[m] * v[m].y);
+            float2 Hn[E];
+            const int zn = z + 1 < z1 ? z + 1 : z0;
+            auto next = [&]() { W::load_row(Hn, bank, zn, t); };
+            F::template run_hook<false>(v, la, lb, tw, t, next);          // G = FFT(g)
             if (want_A) {
-                // reload H_z (an L2 hit) rather than keep it live across both
-                // transforms: the adjoint is register-bound
-                W::load_row(H, bank, z, t);
 #pragma unroll
                 for (int m = 0; m < E; ++m) {                             // acc += conj(H) G
-                    acc[m].x = fmaf(v[m].x, H[m].x, fmaf(v[m].y, H[m].y, acc[m].x));
-                    acc[m].y = fmaf(v[m].y, H[m].x, fmaf(-v[m].x, H[m].y, acc[m].y));
+                    acc[m].x = fmaf(v[m].x, Hc[m].x, fmaf(v[m].y, Hc[m].y, acc[m].x));
+                    acc[m].y = fmaf(v[m].y, Hc[m].x, fmaf(-v[m].x, Hc[m].y, acc[m].y));
                 }
             }
             if (want_T) {
@@ -378,6 +425,9 @@ struct Bwd {
                         pz[p - L + M / 2] = v[m];
                 }
             }
+#pragma unroll
+            for (int m = 0; m < E; ++m)
+                Hc[m] = Hn[m];
         }
         if (want_A) {
             F::template run<true>(acc, la, lb, tw, t);
@@ -389,7 +439,7 @@ struct Bwd {
 };
 
 template <int L>
-__global__ __launch_bounds__(Bwd<L>::T) void backward_kernel(
+__global__ __launch_bounds__(Bwd<L>::T, BwdGeometry<L>::kMinWaves) void backward_kernel(
     const float2* __restrict__ spec, int64_t N, const float2* __restrict__ bank, int K, int M,
     int zchunk, int64_t nwin, const float* __restrict__ dLdP, int want_A, int want_T,
     float2* __restrict__ partA, float2* __restrict__ partT)
@@ -405,8 +455,10 @@ __global__ __launch_bounds__(Bwd<L>::T) void backward_kernel(
     const int c = blockIdx.y;
     const int z0 = c * zchunk;
     const int z1 = min(K, z0 + zchunk);
+    float2 H[Bk::E];
+    Bk::W::load_row(H, bank, z0, t);
     Bk::item(spec, N, bank, M, s, z0, z1, dLdP, want_A != 0, want_T != 0,
-             partA + ((int64_t)c * nwin + s) * L, partT + s * (int64_t)K * M, tw, la, lb, t);
+             partA + ((int64_t)c * nwin + s) * L, partT + s * (int64_t)K * M, tw, la, lb, t, H);
 }
 
 // grad_A[k] = sum over chunks c and windows s covering k of

@@ -8,13 +8,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_1804_05335_amd", "csrc")
 OUT = os.path.join(HERE, "_build", "libfdas_emu.so")
+CXX = "/opt/rocm/llvm/bin/clang++"
 
 
 def build() -> str:
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
     srcs = [os.path.join(CSRC, f) for f in ("fdas_api.cpp", "fdas_templates.cpp", "fdas_kernels.hip")]
     tmp = OUT + f".tmp{os.getpid()}"
-    cmd = ["g++", "-O2", "-std=c++20", "-fPIC", "-shared", "-pthread", "-I", HERE,
+    # clang (ROCm's, as a host compiler): the kernels use clang vector types
+    cmd = [CXX, "-O2", "-std=c++20", "-fPIC", "-shared", "-pthread", "-I", HERE,
            "-I", os.path.join(ROOT, "include"), "-x", "c++"] + srcs + ["-o", tmp]
     subprocess.run(cmd, check=True)
     os.replace(tmp, OUT)

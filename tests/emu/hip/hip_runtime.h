@@ -25,6 +25,58 @@
 
 struct float2 { float x, y; };
 inline float2 make_float2(float a, float b) { return float2{a, b}; }
+
+inline unsigned __float_as_uint(float f) { unsigned u; std::memcpy(&u, &f, 4); return u; }
+inline float __uint_as_float(unsigned u) { float f; std::memcpy(&f, &u, 4); return f; }
+#define __builtin_amdgcn_sched_barrier(x) ((void)0)
+
+// Raw buffer resources: a byte range [base, base + bytes).  As on the GPU,
+// an access whose byte offset is at or past the end is dropped (a load
+// returns 0).  An access that straddles the end would be a kernel bug: it
+// aborts.
+struct EmuRsrc {
+    unsigned char* base;
+    uint32_t bytes;
+};
+#define __amdgpu_buffer_rsrc_t EmuRsrc
+#define __builtin_amdgcn_make_buffer_rsrc emu_make_buffer_rsrc
+#define __builtin_amdgcn_raw_buffer_store_b32 emu_raw_buffer_store_b32
+#define __builtin_amdgcn_raw_buffer_store_b64 emu_raw_buffer_store_b64
+#define __builtin_amdgcn_raw_buffer_load_b32 emu_raw_buffer_load_b32
+inline EmuRsrc emu_make_buffer_rsrc(void* p, short stride, int bytes, int)
+{
+    if (stride != 0 || bytes < 0)
+        std::abort();
+    return EmuRsrc{static_cast<unsigned char*>(p), (uint32_t)bytes};
+}
+inline bool emu_in_range(const EmuRsrc& r, int off, int soff, uint32_t size)
+{
+    const uint32_t o = (uint32_t)off + (uint32_t)soff;
+    if (o >= r.bytes)
+        return false;
+    if (o + size > r.bytes)
+        std::abort();
+    return true;
+}
+inline void emu_raw_buffer_store_b32(unsigned v, EmuRsrc r, int off, int soff, int)
+{
+    if (emu_in_range(r, off, soff, 4))
+        std::memcpy(r.base + (uint32_t)off + (uint32_t)soff, &v, 4);
+}
+template <class V>
+inline void emu_raw_buffer_store_b64(V v, EmuRsrc r, int off, int soff, int)
+{
+    static_assert(sizeof(V) == 8, "64-bit store");
+    if (emu_in_range(r, off, soff, 8))
+        std::memcpy(r.base + (uint32_t)off + (uint32_t)soff, &v, 8);
+}
+inline unsigned emu_raw_buffer_load_b32(EmuRsrc r, int off, int soff, int)
+{
+    unsigned v = 0;
+    if (emu_in_range(r, off, soff, 4))
+        std::memcpy(&v, r.base + (uint32_t)off + (uint32_t)soff, 4);
+    return v;
+}
 struct dim3 {
     unsigned x, y, z;
     dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}

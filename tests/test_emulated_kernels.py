@@ -40,6 +40,25 @@ def _bank(emu, taps, L):
     return bank
 
 
+GUARD = 1 << 14      # floats of sentinel on each side of an output buffer
+SENTINEL = np.float32(-12345.0)
+
+
+def _guarded(shape):
+    """An output array (NaN-filled, so unwritten outputs fail the comparison)
+    inside a larger buffer whose margins hold a sentinel: any store outside
+    the array, before or after it, shows up in the margins."""
+    n = int(np.prod(shape))
+    buf = np.full(n + 2 * GUARD, SENTINEL, dtype=np.float32)
+    buf[GUARD:GUARD + n] = np.nan
+    return buf, buf[GUARD:GUARD + n].reshape(shape)
+
+
+def _check_guards(buf, arr):
+    n = arr.size
+    assert np.all(buf[:GUARD] == SENTINEL) and np.all(buf[GUARD + n:] == SENTINEL)
+
+
 def _rel(got, ref):
     return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
 
@@ -51,9 +70,10 @@ def test_emulated_forward_vs_oracle(emu, L, M, N, grid):
     A = syn.random_spectrum(L + N, N)
     taps = syn.random_taps(M + K, K, M)
     bank = _bank(emu, taps, L)
-    plane = np.full((K, N), np.nan, dtype=np.float32)
+    buf, plane = _guarded((K, N))
     assert emu.fdas_correlate_ex(_p(A), ctypes.c_int64(N), _p(bank), K, M, L, _p(plane),
                                  grid, None) == 0
+    _check_guards(buf, plane)
     assert _rel(plane, native.power(A, taps)) < TOL
 
 
@@ -83,7 +103,7 @@ def test_emulated_batched_equals_plain(emu):
     packed = np.concatenate(specs).astype(np.complex64)
     offs = np.zeros(len(lens) + 1, dtype=np.int64)
     offs[1:] = np.cumsum(lens)
-    planes = np.full(K * offs[-1], np.nan, dtype=np.float32)
+    buf, planes = _guarded((K * offs[-1],))
     emu.fdas_batched_workspace_bytes.restype = ctypes.c_size_t
     wsb = emu.fdas_batched_workspace_bytes(len(lens))
     ws = np.zeros(wsb, dtype=np.uint8)
@@ -92,6 +112,7 @@ def test_emulated_batched_equals_plain(emu):
         assert emu.fdas_correlate_batched_ex(_p(packed), _p(offs), len(lens), _p(bank), K, M, L,
                                              _p(planes), grid, _p(ws), ctypes.c_size_t(wsb),
                                              None) == 0
+        _check_guards(buf, planes)
         for b, n in enumerate(lens):
             if n == 0:
                 continue
@@ -131,7 +152,8 @@ def test_emulated_interbin_vs_oracle(emu, L, M, N, grid):
     A = syn.random_spectrum(7 * L + N, N)
     taps = syn.random_taps(M + 2 * K, K, M)
     bank = _bank(emu, taps, L)
-    plane2 = np.full((K, 2 * N), np.nan, dtype=np.float32)
+    buf, plane2 = _guarded((K, 2 * N))
     assert emu.fdas_correlate_interbin_ex(_p(A), ctypes.c_int64(N), _p(bank), K, M, L,
                                           _p(plane2), grid, None) == 0
+    _check_guards(buf, plane2)
     assert _rel(plane2, direct.interbinned_power(A, taps)) < TOL
