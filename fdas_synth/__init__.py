@@ -182,6 +182,24 @@ def workload(number: int, L: int | None = None, nspec: int | None = None,
     raise ValueError(f"unknown workload {number}")
 
 
+def time_series(seed: int, n: int, signals=(), sigma: float = 1.0,
+                dtype=np.float32) -> np.ndarray:
+    """A real time series of n samples for the real-to-complex front end:
+    white Gaussian noise of standard deviation sigma plus real
+    constant-fdot sinusoids a*cos(phi + 2*pi*(r*u + z*(u*u - u)/2)),
+    u = t/n, from the same signal model as the spectra above.  ``signals``
+    is an iterable of (a, phi, r, z); r is the mid-observation bin."""
+    rng = np.random.default_rng(seed)
+    x = rng.normal(0.0, sigma, n)
+    u = np.arange(n, dtype=np.float64) / n
+    quad = u * u - u
+    for a, phi, r, z in signals:
+        cycles = r * u + 0.5 * z * quad
+        cycles -= np.floor(cycles)
+        x += a * np.cos(phi + 2.0 * np.pi * cycles)
+    return x.astype(dtype)
+
+
 def loss_weights(number: int, K: int, n: int) -> np.ndarray:
     """Loss weights w ~ U(0,1), float32 [K][n], drawn from their own stream
     (seed 1000 + workload number) so the spectrum draws are unaffected."""

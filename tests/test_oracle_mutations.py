@@ -4,7 +4,8 @@ Each mutant below is the oracle with one plausible mistake planted in it
 (here, on the CPU): a dropped conjugate, a window off by one bin, reflected
 taps, the wrong sign of the chirp phase, a symmetric time origin, the
 frequency referenced to the start of the observation, a wrong interbinning
-sign, factor or neighbour, and slips in the adjoint.  For each, at least one
+sign, factor or neighbour, slips in the adjoint, and a wrong exponent sign or
+time origin in the real-to-complex transform.  For each, at least one
 of the pins that guard the oracle must fail, while the oracle itself passes
 all of them -- so the pins can tell these mistakes from the method.
 """
@@ -12,7 +13,7 @@ import numpy as np
 import pytest
 
 import fdas_synth as syn
-from oracle import direct
+from oracle import direct, r2c
 from oracle import templates as ot
 from tests.quadrature import response_quadrature
 
@@ -152,7 +153,31 @@ def grads_unconjugated_taps_gradient(A, T, w):
     return gA, np.conj(gT)
 
 
+def pin_r2c(dft):
+    """Real-to-complex transform: a shifted impulse gives the phase ramp and
+    a cosine on bin k0 gives (n/2) e^{i phi} at k0 (closed forms)."""
+    n, t0, k0, phi = 64, 5, 9, 0.4
+    x = np.zeros(n)
+    x[t0] = 1.0
+    k = np.arange(n // 2 + 1)
+    ok = np.max(np.abs(dft(x) - np.exp(-2j * np.pi * k * t0 / n))) < 1e-12
+    t = np.arange(n)
+    ref = np.zeros(n // 2 + 1, dtype=complex)
+    ref[k0] = 0.5 * n * np.exp(1j * phi)
+    return ok and np.max(np.abs(dft(np.cos(2 * np.pi * k0 * t / n + phi)) - ref)) < 1e-11
+
+
+def r2c_wrong_exponent_sign(x):
+    return np.conj(r2c.dft(x))
+
+
+def r2c_time_index_from_one(x):
+    return r2c.dft(np.roll(np.asarray(x, dtype=np.float64), 1))
+
+
 MUTANTS = {
+    "r2c exponent sign": lambda: pin_r2c(r2c_wrong_exponent_sign),
+    "r2c time origin": lambda: pin_r2c(r2c_time_index_from_one),
     "dropped conj": lambda: pin_chirp(_power_with(corr_dropped_conj), ot.templates),
     "window off by one": lambda: pin_chirp(_power_with(corr_window_off_by_one), ot.templates),
     "reflected taps": lambda: pin_chirp(_power_with(corr_reflected_taps), ot.templates),
@@ -179,6 +204,7 @@ def test_oracle_passes_every_pin():
     assert pin_half_bin(direct.interbinned_power)
     assert pin_half_bin(_ib(lambda y, yn, yp: np.abs((np.pi / 4) * (y - yn)) ** 2))
     assert pin_finite_differences(direct.grads)
+    assert pin_r2c(r2c.dft)
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
