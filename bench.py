@@ -327,6 +327,34 @@ def bench_workload5(fdas, torch, steps: int):
     return out
 
 
+def bench_r2c(fdas, torch, steps: int):
+    """Real-to-complex front end on 2^22, 2^23 and 2^24 FP32 samples (the
+    paper's signal lengths): time per call with the series resident in HBM,
+    against the algorithmic bytes (read 4n, write 8(n/2 + 1))."""
+    import fdas_synth as syn
+    out = {}
+    for log2n in (22, 23, 24):
+        n = 1 << log2n
+        x = torch.from_numpy(syn.time_series(log2n, n)).cuda()
+        spec = torch.empty(n // 2 + 1, dtype=torch.complex64, device="cuda")
+        ws = torch.empty(fdas.fdas_r2c_workspace_bytes(n), dtype=torch.uint8, device="cuda")
+
+        def call():
+            fdas.fdas_r2c(x, n, 1.0, spec, ws)
+
+        for _ in range(3):
+            call()
+        ms = _timed(torch, call, max(steps, 10))
+        alg = 4 * n + 8 * (n // 2 + 1)
+        out[f"2^{log2n}"] = {"ms": ms, "samples_per_s": n / ms * 1e3,
+                             "algorithmic_GB_per_s": alg / ms / 1e6,
+                             "hbm_frac": alg / ms / 1e6 / HBM_PEAK_GBS}
+        del x, spec, ws
+    torch.cuda.empty_cache()
+    out["paper_cpu_r2c_ms"] = {"2^21": 30, "2^22": 75, "2^23": 220}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -339,7 +367,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and forward+backward comparisons")
-    ap.add_argument("--extras", default="batched,fwd_bwd,large_zmax",
+    ap.add_argument("--extras", default="batched,fwd_bwd,large_zmax,r2c",
                     help="comma-separated extra comparisons to run")
     ap.add_argument("--extra-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -434,7 +462,8 @@ def main() -> int:
     }
     del plane
     torch.cuda.empty_cache()
-    extras = {"batched": bench_batched, "fwd_bwd": bench_fwd_bwd, "large_zmax": bench_workload5}
+    extras = {"batched": bench_batched, "fwd_bwd": bench_fwd_bwd, "large_zmax": bench_workload5,
+              "r2c": bench_r2c}
     for name in ([] if args.no_extras else [x for x in args.extras.split(",") if x]):
         out[name] = extras[name](fdas, torch, args.extra_steps)
         print(f"# {name}: {json.dumps(out[name])}", file=sys.stderr, flush=True)

@@ -258,6 +258,32 @@ int fdas_autotune_batched(const fdas_cf32 *taps_dev, int K, int M, const fdas_cf
                           size_t ws_bytes, hipStream_t stream, int *L_out, int *grid_out,
                           double *ms_out);
 
+/* ---- real-to-complex front end -------------------------------------------- */
+
+/* Bytes of device workspace fdas_r2c needs for n samples (0 if n is not
+ * supported): n/2 complex work values plus two twiddle tables of about
+ * 2 sqrt(n) entries. */
+size_t fdas_r2c_workspace_bytes(int64_t n);
+
+/*
+ * Real-to-complex transform of a time series (Sec. 4.1: the input is an
+ * array of n FP32 samples taken to the Fourier domain by a real-to-complex
+ * FFT; Sec. 3 lists it as the first processing step):
+ *     spec[k] = scale * sum_{t=0}^{n-1} x[t] exp(-2 pi i k t / n),
+ *     k = 0 .. n/2   (n/2 + 1 bins, the Nyquist bin included).
+ * scale = 1 is the unnormalised transform; 1/sqrt(n) gives bins of unit
+ * mean power for unit-variance white noise.  The first n/2 bins are a
+ * spectrum for fdas_correlate (N = n/2) or the whole array (N = n/2 + 1).
+ *  x_dev     n floats, 8-byte aligned, read only.
+ *  n         a power of two in [2^13, 2^27]; else FDAS_UNSUPPORTED.
+ *  spec_dev  n/2 + 1 fdas_cf32, 8-byte aligned, fully overwritten (also used
+ *            as scratch during the call); must not overlap x_dev or ws_dev.
+ *  ws_dev    fdas_r2c_workspace_bytes(n) bytes, 256-byte aligned.
+ * Asynchronous on `stream`; no allocation.
+ */
+int fdas_r2c(const float *x_dev, int64_t n, float scale, fdas_cf32 *spec_dev, void *ws_dev,
+             size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -36,3 +36,17 @@ def spectrum(x, scale: float = 1.0) -> np.ndarray:
     """The same bins via numpy's real FFT in FP64 (complex128)."""
     x = np.asarray(x, dtype=np.float64)
     return scale * np.fft.rfft(x)
+
+
+def dft_points(x, ks, scale: float = 1.0) -> np.ndarray:
+    """The literal sum at the selected bins ks only (complex128), O(n) per
+    bin, for sampled checks at sizes where the full literal sum is out of
+    reach."""
+    x = np.asarray(x, dtype=np.float64)
+    n = len(x)
+    t = np.arange(n, dtype=np.int64)
+    out = np.empty(len(ks), dtype=np.complex128)
+    for i, k in enumerate(np.asarray(ks, dtype=np.int64)):
+        ph = (k * t) % n
+        out[i] = np.dot(np.exp(-2j * np.pi * ph / n), x)
+    return scale * out

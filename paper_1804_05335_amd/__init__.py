@@ -16,7 +16,8 @@ from ._lib import (FdasError, fdas_backward_workspace_bytes, fdas_bank_elems,  #
                    fdas_correlate_batched_ex, fdas_correlate_ex, fdas_correlate_interbin,
                    fdas_correlate_interbin_ex, fdas_make_templates,
                    fdas_make_templates_host, fdas_num_templates, fdas_prepare_bank,
-                   fdas_template_response, fdas_version, lib)
+                   fdas_r2c, fdas_r2c_workspace_bytes, fdas_template_response, fdas_version,
+                   lib)
 
 
 def make_bank(zmax: float, dz: float, M: int, L: int, device="cuda"):
@@ -92,3 +93,17 @@ def correlate_batched(specs, offsets, bank, K: int, M: int, L: int, planes=None,
                          device=specs.device)
     fdas_correlate_batched_ex(specs, offsets, nspec, bank, K, M, L, planes, grid, ws)
     return planes
+
+
+def spectrum_from_series(x, scale: float = 1.0, spec=None, ws=None):
+    """Real-to-complex transform of a float32 device time series of n
+    samples: the n/2 + 1 bins scale * sum_t x[t] exp(-2 pi i k t / n).
+    ``spec`` and the workspace ``ws`` are allocated when not given."""
+    import torch
+    n = x.numel()
+    if spec is None:
+        spec = torch.empty(n // 2 + 1, dtype=torch.complex64, device=x.device)
+    if ws is None:
+        ws = torch.empty(max(fdas_r2c_workspace_bytes(n), 1), dtype=torch.uint8, device=x.device)
+    fdas_r2c(x, n, scale, spec, ws)
+    return spec

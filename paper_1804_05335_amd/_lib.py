@@ -50,6 +50,8 @@ SIGNATURES = [
     ("fdas_backward_workspace_bytes", _SZ, [_I64, _I, _I, _I, _I]),
     ("fdas_correlate_backward", _I, [_P, _I64, _P, _I, _I, _I, _P, _P, _P, _P, _SZ, _P]),
     ("fdas_correlate_backward_ex", _I, [_P, _I64, _P, _I, _I, _I, _P, _P, _P, _I, _P, _SZ, _P]),
+    ("fdas_r2c_workspace_bytes", _SZ, [_I64]),
+    ("fdas_r2c", _I, [_P, _I64, ctypes.c_float, _P, _P, _SZ, _P]),
 ]
 
 
@@ -269,3 +271,16 @@ def fdas_autotune_batched(taps, K: int, M: int, specs, offsets, nspec: int, plan
                                        ctypes.byref(Lo), ctypes.byref(go), ctypes.byref(ms)),
            "fdas_autotune_batched")
     return Lo.value, go.value, ms.value
+
+
+def fdas_r2c_workspace_bytes(n: int) -> int:
+    return int(lib().fdas_r2c_workspace_bytes(n))
+
+
+def fdas_r2c(x, n: int, scale: float, spec, ws, stream=None) -> None:
+    import torch
+    _require(x, torch.float32, "x", n)
+    _require(spec, torch.complex64, "spec", n // 2 + 1)
+    _require(ws, torch.uint8, "ws", fdas_r2c_workspace_bytes(n))
+    _check(lib().fdas_r2c(_ptr(x), n, scale, _ptr(spec), _ptr(ws), ws.numel(),
+                          _stream(stream, x)), "fdas_r2c")

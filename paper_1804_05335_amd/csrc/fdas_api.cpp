@@ -404,3 +404,61 @@ int fdas_correlate_backward(const fdas_cf32* spec_dev, int64_t N, const fdas_cf3
 }
 
 }  // extern "C"
+
+// ---- real-to-complex front end ----------------------------------------------
+
+namespace {
+
+// log2(n) for a supported time-series length, else -1.
+int r2c_log2n(int64_t n)
+{
+    if (n < ((int64_t)1 << 13) || n > ((int64_t)1 << 27) || (n & (n - 1)) != 0)
+        return -1;
+    int l = 0;
+    while (((int64_t)1 << l) < n)
+        ++l;
+    int bits[4];
+    return fdas::r2c_plan(l - 1, bits) > 0 ? l : -1;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fdas_r2c_workspace_bytes(int64_t n)
+{
+    const int l = r2c_log2n(n);
+    if (l < 0)
+        return 0;
+    return ((size_t)(n / 2) + fdas::r2c_table_elems(l)) * sizeof(fdas_cf32);
+}
+
+int fdas_r2c(const float* x_dev, int64_t n, float scale, fdas_cf32* spec_dev, void* ws_dev,
+             size_t ws_bytes, hipStream_t stream)
+{
+    const int l = r2c_log2n(n);
+    if (l < 0)
+        return fail(FDAS_UNSUPPORTED, "n = %lld is not a power of two in [2^13, 2^27]",
+                    (long long)n);
+    if (!x_dev || !spec_dev || !ws_dev)
+        return fail(FDAS_INVALID_ARG, "x, spec and ws must not be NULL");
+    if (!aligned(x_dev, 8) || !aligned(spec_dev, 8) || !aligned(ws_dev, 256))
+        return fail(FDAS_INVALID_ARG, "misaligned pointer (x and spec 8 B, ws 256 B)");
+    const size_t need = fdas_r2c_workspace_bytes(n);
+    if (ws_bytes < need)
+        return fail(FDAS_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", ws_bytes,
+                    need);
+    const auto xb = reinterpret_cast<uintptr_t>(x_dev), sb = reinterpret_cast<uintptr_t>(spec_dev),
+               wb = reinterpret_cast<uintptr_t>(ws_dev);
+    const uintptr_t xe = xb + (uintptr_t)n * 4, se = sb + (uintptr_t)(n / 2 + 1) * 8,
+                    we = wb + need;
+    if ((xb < se && sb < xe) || (xb < we && wb < xe) || (sb < we && wb < se))
+        return fail(FDAS_INVALID_ARG, "x, spec and ws must not overlap");
+    hipError_t e = fdas::launch_r2c(x_dev, l, scale, reinterpret_cast<float2*>(spec_dev),
+                                    reinterpret_cast<float2*>(ws_dev), stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "r2c launch");
+    return ok();
+}
+
+}  // extern "C"

@@ -160,3 +160,24 @@ def test_autotune_validation_before_any_device_call():
     assert L.fdas_autotune_batched(*args(p, wsb, M=255)) == _lib.FDAS_INVALID_ARG
     assert L.fdas_autotune_batched(p, 85, 256, p, p, 4, p, p, wsb, None, None,
                                    ctypes.byref(go), None) == _lib.FDAS_INVALID_ARG
+
+
+def test_r2c_validation_before_any_device_call():
+    L = _lib.lib()
+    n = 1 << 20
+    wsb = L.fdas_r2c_workspace_bytes(n)
+    assert wsb >= (n // 2) * 8
+    for bad in (0, 1 << 12, (1 << 20) + 2, 3 << 18, 1 << 28, -4):
+        assert L.fdas_r2c_workspace_bytes(bad) == 0
+        assert L.fdas_r2c(_fake(0x10000), bad, 1.0, _fake(0x4000000), _fake(0x8000000), wsb,
+                          None) == _lib.FDAS_UNSUPPORTED
+    x, spec, ws = _fake(0x10000000), _fake(0x20000000), _fake(0x30000000)
+    assert L.fdas_r2c(x, n, 1.0, spec, ws, wsb - 1, None) == _lib.FDAS_WORKSPACE_TOO_SMALL
+    assert L.fdas_r2c(None, n, 1.0, spec, ws, wsb, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_r2c(_fake(0x10000004), n, 1.0, spec, ws, wsb, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_r2c(x, n, 1.0, spec, _fake(0x30000080), wsb, None) == _lib.FDAS_INVALID_ARG
+    # overlapping buffers: spec inside x, ws overlapping spec
+    assert L.fdas_r2c(x, n, 1.0, _fake(0x10000000 + 8 * 1024), ws, wsb, None) == \
+        _lib.FDAS_INVALID_ARG
+    assert L.fdas_r2c(x, n, 1.0, spec, _fake(0x20000000 + 4096 * 256), wsb, None) == \
+        _lib.FDAS_INVALID_ARG

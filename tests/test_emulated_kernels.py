@@ -157,3 +157,26 @@ def test_emulated_interbin_vs_oracle(emu, L, M, N, grid):
                                           _p(plane2), grid, None) == 0
     _check_guards(buf, plane2)
     assert _rel(plane2, direct.interbinned_power(A, taps)) < TOL
+
+
+@pytest.mark.parametrize("log2n", [13, 14, 15, 16, 17, 18])
+def test_emulated_r2c_vs_oracle(emu, log2n):
+    # plans: 2^12 complex points -> radix bits (6, 6); ... 2^17 -> (6, 6, 5),
+    # so every radix 32..256 and both pass kinds run
+    from oracle import r2c
+    n = 1 << log2n
+    x = syn.time_series(log2n, n, [(0.3, 0.2, n / 7 + 0.4, 11.0)])
+    emu.fdas_r2c_workspace_bytes.restype = ctypes.c_size_t
+    wsb = emu.fdas_r2c_workspace_bytes(ctypes.c_int64(n))
+    assert wsb > 0
+    ws = np.zeros(wsb + 256, dtype=np.uint8)
+    wsp = ctypes.c_void_p((ws.ctypes.data + 255) & ~255)
+    buf, spec = _guarded((n + 2,))            # n/2 + 1 complex values as float pairs
+    scale = 1.0 / np.sqrt(n)
+    assert emu.fdas_r2c(_p(x), ctypes.c_int64(n), ctypes.c_float(scale), _p(spec), wsp,
+                        ctypes.c_size_t(wsb), None) == 0
+    _check_guards(buf, spec)
+    got = spec.view(np.complex64).astype(np.complex128)
+    ref = r2c.spectrum(x, scale)
+    assert np.max(np.abs(got - ref)) < TOL * np.max(np.abs(ref))
+    assert np.linalg.norm(got - ref) < 1e-6 * np.linalg.norm(ref)

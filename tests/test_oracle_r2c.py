@@ -99,3 +99,10 @@ def test_fft_route_matches_literal_sum(n):
     x = _series(n, n)
     a, b = r2c.spectrum(x, scale=0.25), r2c.dft(x, scale=0.25)
     assert np.max(np.abs(a - b)) < 1e-12 * max(1.0, np.max(np.abs(b)))
+
+
+def test_dft_points_match_literal_sum():
+    n = 512
+    x = _series(9, n)
+    ks = np.array([0, 1, 17, 255, 256])
+    assert np.max(np.abs(r2c.dft_points(x, ks, 0.5) - r2c.dft(x, 0.5)[ks])) < 1e-10
