@@ -327,6 +327,40 @@ def bench_workload5(fdas, torch, steps: int):
     return out
 
 
+def bench_interbin(fdas, torch, steps: int):
+    """Interbinned plane ([K][2N], eq. f-interp) against the plain plane on
+    the headline workload (2^21 bins, 85 x 256 taps, segment 2048); the
+    paper quotes interbinning at 1.1-1.6 times the plain run (Sec. 5)."""
+    import fdas_synth as syn
+    w = syn.workload(2)
+    K, M, L = w.K, w.M, 2048
+    N = len(w.spectra[0])
+    spec = torch.from_numpy(w.spectra[0]).cuda()
+    _, bank = fdas.make_bank(w.zmax, w.dz, M, L)
+    plane = torch.empty((K, N), dtype=torch.float32, device="cuda")
+    plane2 = torch.empty((K, 2 * N), dtype=torch.float32, device="cuda")
+
+    def plain():
+        fdas.fdas_correlate(spec, N, bank, K, M, L, plane)
+
+    def ib():
+        fdas.fdas_correlate_interbin(spec, N, bank, K, M, L, plane2)
+
+    for f in (plain, ib):
+        for _ in range(5):
+            f()
+    ms_p = _timed(torch, plain, max(steps, 10))
+    ms_i = _timed(torch, ib, max(steps, 10))
+    bytes_i = 8 * N + 8 * K * N + 8 * K * L
+    out = {"workload": f"2^21 bins, {K} templates x {M} taps, segment {L}",
+           "plain_ms": ms_p, "interbinned_ms": ms_i, "interbinned_over_plain": ms_i / ms_p,
+           "interbinned_points_per_s": 2 * K * N / ms_i * 1e3,
+           "interbinned_algorithmic_GB_per_s": bytes_i / ms_i / 1e6}
+    del spec, plane, plane2
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_r2c(fdas, torch, steps: int):
     """Real-to-complex front end on 2^22, 2^23 and 2^24 FP32 samples (the
     paper's signal lengths): time per call with the series resident in HBM,
@@ -367,7 +401,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and forward+backward comparisons")
-    ap.add_argument("--extras", default="batched,fwd_bwd,large_zmax,r2c",
+    ap.add_argument("--extras", default="batched,fwd_bwd,large_zmax,interbin,r2c",
                     help="comma-separated extra comparisons to run")
     ap.add_argument("--extra-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -463,7 +497,7 @@ def main() -> int:
     del plane
     torch.cuda.empty_cache()
     extras = {"batched": bench_batched, "fwd_bwd": bench_fwd_bwd, "large_zmax": bench_workload5,
-              "r2c": bench_r2c}
+              "interbin": bench_interbin, "r2c": bench_r2c}
     for name in ([] if args.no_extras else [x for x in args.extras.split(",") if x]):
         out[name] = extras[name](fdas, torch, args.extra_steps)
         print(f"# {name}: {json.dumps(out[name])}", file=sys.stderr, flush=True)

@@ -255,12 +255,23 @@ struct TwiddleCount<L, E, NS, Radices<R, Rest...>> {
                                  TwiddleCount<L, E, NS * R, Radices<Rest...>>::value;
 };
 
-// LDS index with one complex of padding every 16 (breaks power-of-two strides).
-__device__ __forceinline__ int lds_pad(int idx) { return idx + (idx >> 4); }
+// LDS index: the low five bits (32 complex values = 64 banks) XORed with a
+// function g of the 32-value block number h.  A bijection on [0, L), so no
+// padding.  A contiguous 32-value row stays a permutation of the banks; for
+// the exchanges' writes -- stride R in the first pass, blocks NS apart
+// later -- g's low three bits follow h and bits 3, 4 fold h's bit 3 into
+// bits 1, 2, which keeps each half-wave on distinct banks for the E = 8 and
+// E = 16 plans.
+__device__ __forceinline__ int lds_pad(int idx)
+{
+    const int h = idx >> 5;
+    const int g = (h & 7) | ((((h >> 1) ^ (h >> 3)) & 1) << 3) | ((((h >> 2) ^ (h >> 3)) & 1) << 4);
+    return idx ^ g;
+}
 
 template <int L>
 struct LdsSize {
-    static constexpr int value = L + L / 16;
+    static constexpr int value = L;
 };
 
 // Load the twiddles for passes NS.. into tw[OFF..].

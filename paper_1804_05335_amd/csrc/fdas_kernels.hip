@@ -167,7 +167,15 @@ struct Fwd {
             float2 v[E];
             const int znext = z + 1 == K ? 0 : z + 1;
             auto next = [&]() { load_row(H, bank, znext, t); };
-            F::template run_mul_hook<true, kMul>(X, H, v, la, lb, tw, t, next);
+            if constexpr (!IB) {
+                F::template run_mul_hook<true, kMul>(X, H, v, la, lb, tw, t, next);
+            } else {
+                // the interbinned epilogue holds more values; the next row is
+                // loaded once y has gone to LDS, which keeps H out of the
+                // transform's register peak
+                NoHook none;
+                F::template run_mul_hook<true, kMul>(X, H, v, la, lb, tw, t, none);
+            }
             if constexpr (!IB) {
                 const float* row_q0 = plane + ((int64_t)z * N + out0 - M / 2);
                 const auto rs = seg_rsrc(row_q0, (M / 2 + nvalid) * 4);
@@ -182,6 +190,7 @@ struct Fwd {
 #pragma unroll
                 for (int m = 0; m < E; ++m)
                     la[lds_pad(t + T * m)] = v[m];
+                next();
                 __syncthreads();
                 // both y_r and y_{r+1} are read back from LDS so v is dead here;
                 // for valid outputs q + 1 <= M/2 + B = L - M/2 stays inside the

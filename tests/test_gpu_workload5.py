@@ -64,7 +64,10 @@ def test_workload5_batched_forward_sampled(fd, w5):
                    torch.from_numpy(ri).cuda()].cpu().numpy()
         ref = native.power_points(w5.spectra[b], T, zi, ri)
         assert _rel(got, ref) < TOL, b
-    assert bool(torch.isfinite(planes).all())
+    # checked in slices: an elementwise mask of the whole ~146 GB plane would
+    # not fit next to it
+    for part in planes.split(1 << 30):
+        assert bool(torch.isfinite(part).all())
     del planes
     torch.cuda.empty_cache()
 
