@@ -361,6 +361,41 @@ def bench_interbin(fdas, torch, steps: int):
     return out
 
 
+def bench_sym(fdas, torch, steps: int):
+    """Full bank against the symmetric bank (rows z >= 0 only, +/-z symmetry)
+    on one spectrum of the large-zmax geometry: 201 templates x 512 taps,
+    segments 2048, 4096 and 8192 (full bank 3.3, 6.6 and 13.2 MB)."""
+    import fdas_synth as syn
+    w = syn.workload(5, nspec=1)
+    K, M = w.K, w.M
+    N = len(w.spectra[0])
+    spec = torch.from_numpy(w.spectra[0]).cuda()
+    plane = torch.empty((K, N), dtype=torch.float32, device="cuda")
+    out = {"workload": f"{N} bins, {K} templates x {M} taps"}
+    for L in (2048, 4096, 8192):
+        taps, bank = fdas.make_bank(w.zmax, w.dz, M, L)
+        sym = fdas.prepare_bank_sym(taps, L)
+
+        def full():
+            fdas.fdas_correlate(spec, N, bank, K, M, L, plane)
+
+        def half():
+            fdas.fdas_correlate_sym(spec, N, sym, K, M, L, plane)
+
+        for f in (full, half):
+            for _ in range(3):
+                f()
+        ms_f = _timed(torch, full, max(steps, 5))
+        ms_s = _timed(torch, half, max(steps, 5))
+        out[str(L)] = {"full_bank_ms": ms_f, "symmetric_bank_ms": ms_s,
+                       "full_bank_MB": bank.numel() * 8 / 1e6, "symmetric_bank_MB": sym.numel() * 8 / 1e6,
+                       "points_per_s_symmetric": K * N / ms_s * 1e3}
+        del bank, sym
+    del spec, plane
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_r2c(fdas, torch, steps: int):
     """Real-to-complex front end on 2^22, 2^23 and 2^24 FP32 samples (the
     paper's signal lengths): time per call with the series resident in HBM,
@@ -401,7 +436,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and forward+backward comparisons")
-    ap.add_argument("--extras", default="batched,fwd_bwd,large_zmax,interbin,r2c",
+    ap.add_argument("--extras", default="batched,fwd_bwd,large_zmax,interbin,sym,r2c",
                     help="comma-separated extra comparisons to run")
     ap.add_argument("--extra-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -497,7 +532,7 @@ def main() -> int:
     del plane
     torch.cuda.empty_cache()
     extras = {"batched": bench_batched, "fwd_bwd": bench_fwd_bwd, "large_zmax": bench_workload5,
-              "interbin": bench_interbin, "r2c": bench_r2c}
+              "interbin": bench_interbin, "sym": bench_sym, "r2c": bench_r2c}
     for name in ([] if args.no_extras else [x for x in args.extras.split(",") if x]):
         out[name] = extras[name](fdas, torch, args.extra_steps)
         print(f"# {name}: {json.dumps(out[name])}", file=sys.stderr, flush=True)

@@ -155,7 +155,7 @@ int fdas_correlate_ex(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf32 *ban
  *     plane2[z][2r+1] = |(pi/4)(Y[z][r] - Y[z][r+1])|^2,
  * where Y[z][N] is the same correlation sum one bin past the end (the
  * spectrum is zero outside [0, N)).  Arguments and errors as
- * fdas_correlate; plane2_dev holds K*2N floats, 4-byte aligned.
+ * fdas_correlate; plane2_dev holds K*2N floats, 8-byte aligned.
  */
 int fdas_correlate_interbin(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf32 *bank_dev,
                             int K, int M, int L, float *plane2_dev, hipStream_t stream);
@@ -164,6 +164,32 @@ int fdas_correlate_interbin(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf3
 int fdas_correlate_interbin_ex(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf32 *bank_dev,
                                int K, int M, int L, float *plane2_dev, int grid,
                                hipStream_t stream);
+
+/*
+ * Symmetric bank (Sec. 4.2 notes that the templates of -z are the complex
+ * conjugates of those of +z).  On the grid z_k = (k - (K-1)/2) dz with K
+ * odd, T[K-1-k][j] = conj(T[k][j]), so the prepared filters satisfy
+ * H_{-z}[p] = conj(H_z[(L - p) mod L]): only the (K+1)/2 rows z >= 0 are
+ * stored, ((K+1)/2 + 1) * L complex values with the twiddle row last, and
+ * the forward reads row -z as the conjugate mirror of row z.  This halves
+ * the bank's memory and cache footprint; it removes no transform (for a
+ * complex spectrum Y_z and Y_{-z} are inverse transforms of different
+ * products).
+ *
+ * fdas_bank_sym_elems: elements of such a bank (0 if K is even or < 1).
+ * fdas_prepare_bank_sym: as fdas_prepare_bank, reading only the taps of the
+ *   templates k >= (K-1)/2 (taps_dev still holds all K rows); K must be
+ *   odd (else FDAS_INVALID_ARG).  The caller asserts the symmetry above,
+ *   which fdas_make_templates' taps satisfy.
+ * fdas_correlate_sym(_ex): fdas_correlate(_ex) with such a bank; same plane.
+ */
+int64_t fdas_bank_sym_elems(int K, int L);
+int fdas_prepare_bank_sym(const fdas_cf32 *taps_dev, int K, int M, int L, fdas_cf32 *bank_dev,
+                          hipStream_t stream);
+int fdas_correlate_sym(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf32 *bank_sym_dev, int K,
+                       int M, int L, float *plane_dev, hipStream_t stream);
+int fdas_correlate_sym_ex(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf32 *bank_sym_dev,
+                          int K, int M, int L, float *plane_dev, int grid, hipStream_t stream);
 
 /* Bytes of device workspace fdas_correlate_batched needs for nspec spectra
  * (the per-spectrum segment prefix sums), rounded up to 256. */

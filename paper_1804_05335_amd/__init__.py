@@ -17,7 +17,8 @@ from ._lib import (FdasError, fdas_backward_workspace_bytes, fdas_bank_elems,  #
                    fdas_correlate_interbin_ex, fdas_make_templates,
                    fdas_make_templates_host, fdas_num_templates, fdas_prepare_bank,
                    fdas_r2c, fdas_r2c_workspace_bytes, fdas_template_response, fdas_version,
-                   lib)
+                   fdas_bank_sym_elems, fdas_correlate_sym, fdas_correlate_sym_ex,
+                   fdas_prepare_bank_sym, lib)
 
 
 def make_bank(zmax: float, dz: float, M: int, L: int, device="cuda"):
@@ -107,3 +108,22 @@ def spectrum_from_series(x, scale: float = 1.0, spec=None, ws=None):
         ws = torch.empty(max(fdas_r2c_workspace_bytes(n), 1), dtype=torch.uint8, device=x.device)
     fdas_r2c(x, n, scale, spec, ws)
     return spec
+
+
+def prepare_bank_sym(taps, L: int):
+    """Symmetric bank (rows z >= 0 only) from K x M templates, K odd."""
+    import torch
+    K, M = taps.shape
+    bank = torch.empty(fdas_bank_sym_elems(K, L), dtype=torch.complex64, device=taps.device)
+    fdas_prepare_bank_sym(taps.contiguous(), K, M, L, bank)
+    return bank
+
+
+def correlate_sym(spec, bank_sym, K: int, M: int, L: int, plane=None, grid: int = 0):
+    """fdas_correlate with a symmetric bank: the same K x N plane."""
+    import torch
+    N = spec.numel()
+    if plane is None:
+        plane = torch.empty((K, N), dtype=torch.float32, device=spec.device)
+    fdas_correlate_sym_ex(spec, N, bank_sym, K, M, L, plane, grid)
+    return plane

@@ -50,6 +50,10 @@ SIGNATURES = [
     ("fdas_backward_workspace_bytes", _SZ, [_I64, _I, _I, _I, _I]),
     ("fdas_correlate_backward", _I, [_P, _I64, _P, _I, _I, _I, _P, _P, _P, _P, _SZ, _P]),
     ("fdas_correlate_backward_ex", _I, [_P, _I64, _P, _I, _I, _I, _P, _P, _P, _I, _P, _SZ, _P]),
+    ("fdas_bank_sym_elems", _I64, [_I, _I]),
+    ("fdas_prepare_bank_sym", _I, [_P, _I, _I, _I, _P, _P]),
+    ("fdas_correlate_sym", _I, [_P, _I64, _P, _I, _I, _I, _P, _P]),
+    ("fdas_correlate_sym_ex", _I, [_P, _I64, _P, _I, _I, _I, _P, _I, _P]),
     ("fdas_r2c_workspace_bytes", _SZ, [_I64]),
     ("fdas_r2c", _I, [_P, _I64, ctypes.c_float, _P, _P, _SZ, _P]),
 ]
@@ -284,3 +288,30 @@ def fdas_r2c(x, n: int, scale: float, spec, ws, stream=None) -> None:
     _require(ws, torch.uint8, "ws", fdas_r2c_workspace_bytes(n))
     _check(lib().fdas_r2c(_ptr(x), n, scale, _ptr(spec), _ptr(ws), ws.numel(),
                           _stream(stream, x)), "fdas_r2c")
+
+
+def fdas_bank_sym_elems(K: int, L: int) -> int:
+    return int(lib().fdas_bank_sym_elems(K, L))
+
+
+def fdas_prepare_bank_sym(taps, K: int, M: int, L: int, bank_sym, stream=None) -> None:
+    import torch
+    _require(taps, torch.complex64, "taps", K * M)
+    _require(bank_sym, torch.complex64, "bank_sym", fdas_bank_sym_elems(K, L))
+    _check(lib().fdas_prepare_bank_sym(_ptr(taps), K, M, L, _ptr(bank_sym), _stream(stream, taps)),
+           "fdas_prepare_bank_sym")
+
+
+def fdas_correlate_sym(spec, N: int, bank_sym, K: int, M: int, L: int, plane,
+                       stream=None) -> None:
+    fdas_correlate_sym_ex(spec, N, bank_sym, K, M, L, plane, 0, stream)
+
+
+def fdas_correlate_sym_ex(spec, N: int, bank_sym, K: int, M: int, L: int, plane, grid: int,
+                          stream=None) -> None:
+    import torch
+    _require(spec, torch.complex64, "spec", N)
+    _require(bank_sym, torch.complex64, "bank_sym", fdas_bank_sym_elems(K, L))
+    _require(plane, torch.float32, "plane", K * N)
+    _check(lib().fdas_correlate_sym_ex(_ptr(spec), N, _ptr(bank_sym), K, M, L, _ptr(plane), grid,
+                                       _stream(stream, spec)), "fdas_correlate_sym")

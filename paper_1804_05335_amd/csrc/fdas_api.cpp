@@ -218,11 +218,13 @@ int fdas_make_templates(double zmax, double dz, int M, int L, fdas_cf32* taps_de
 namespace {
 
 int correlate_impl(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* bank_dev, int K, int M,
-                   int L, float* plane_dev, int grid, bool interbin, hipStream_t stream)
+                   int L, float* plane_dev, int grid, bool interbin, bool sym, hipStream_t stream)
 {
     int st = check_geometry(K, M, L);
     if (st)
         return st;
+    if (sym && !(K & 1))
+        return fail(FDAS_INVALID_ARG, "a symmetric bank needs an odd K (got %d)", K);
     if (N < 0 || N > kMaxN)
         return fail(FDAS_INVALID_ARG, "N = %lld outside [0, 2^32]", (long long)N);
     if (grid < 0 || grid > kMaxGrid)
@@ -231,11 +233,12 @@ int correlate_impl(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* bank_d
         return ok();
     if (!spec_dev || !bank_dev || !plane_dev)
         return fail(FDAS_INVALID_ARG, "spec_dev, bank_dev and plane_dev must not be NULL");
-    if (!aligned(spec_dev, 8) || !aligned(bank_dev, 16) || !aligned(plane_dev, 4))
-        return fail(FDAS_INVALID_ARG, "misaligned pointer (spec 8 B, bank 16 B, plane 4 B)");
+    if (!aligned(spec_dev, 8) || !aligned(bank_dev, 16) || !aligned(plane_dev, interbin ? 8 : 4))
+        return fail(FDAS_INVALID_ARG,
+                    "misaligned pointer (spec 8 B, bank 16 B, plane 4 B, interbinned plane 8 B)");
     hipError_t e = fdas::launch_forward(reinterpret_cast<const float2*>(spec_dev), N,
                                         reinterpret_cast<const float2*>(bank_dev), K, M, L,
-                                        plane_dev, grid, interbin, stream);
+                                        plane_dev, grid, interbin, sym, stream);
     if (e != hipSuccess)
         return hip_fail(e, "forward launch");
     return ok();
@@ -248,26 +251,68 @@ extern "C" {
 int fdas_correlate_ex(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* bank_dev, int K,
                       int M, int L, float* plane_dev, int grid, hipStream_t stream)
 {
-    return correlate_impl(spec_dev, N, bank_dev, K, M, L, plane_dev, grid, false, stream);
+    return correlate_impl(spec_dev, N, bank_dev, K, M, L, plane_dev, grid, false, false, stream);
 }
 
 int fdas_correlate(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* bank_dev, int K, int M,
                    int L, float* plane_dev, hipStream_t stream)
 {
-    return correlate_impl(spec_dev, N, bank_dev, K, M, L, plane_dev, 0, false, stream);
+    return correlate_impl(spec_dev, N, bank_dev, K, M, L, plane_dev, 0, false, false, stream);
 }
 
 int fdas_correlate_interbin_ex(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* bank_dev,
                                int K, int M, int L, float* plane2_dev, int grid,
                                hipStream_t stream)
 {
-    return correlate_impl(spec_dev, N, bank_dev, K, M, L, plane2_dev, grid, true, stream);
+    return correlate_impl(spec_dev, N, bank_dev, K, M, L, plane2_dev, grid, true, false, stream);
 }
 
 int fdas_correlate_interbin(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* bank_dev,
                             int K, int M, int L, float* plane2_dev, hipStream_t stream)
 {
-    return correlate_impl(spec_dev, N, bank_dev, K, M, L, plane2_dev, 0, true, stream);
+    return correlate_impl(spec_dev, N, bank_dev, K, M, L, plane2_dev, 0, true, false, stream);
+}
+
+int64_t fdas_bank_sym_elems(int K, int L)
+{
+    if (K < 1 || !(K & 1) || L < 1)
+        return 0;
+    return (int64_t)((K + 1) / 2 + 1) * (int64_t)L;
+}
+
+int fdas_prepare_bank_sym(const fdas_cf32* taps_dev, int K, int M, int L, fdas_cf32* bank_dev,
+                          hipStream_t stream)
+{
+    int st = check_geometry(K, M, L);
+    if (st)
+        return st;
+    if (!(K & 1))
+        return fail(FDAS_INVALID_ARG, "a symmetric bank needs an odd K (got %d)", K);
+    if (!taps_dev || !bank_dev)
+        return fail(FDAS_INVALID_ARG, "taps_dev and bank_dev must not be NULL");
+    if (!aligned(taps_dev, 8) || !aligned(bank_dev, 16))
+        return fail(FDAS_INVALID_ARG, "taps_dev must be 8-byte and bank_dev 16-byte aligned");
+    // rows z >= 0 are templates (K-1)/2 .. K-1
+    const int c = (K - 1) / 2;
+    hipError_t e = fdas::launch_prepare_bank(
+        reinterpret_cast<const float2*>(taps_dev) + (size_t)c * M, K - c, M, L,
+        reinterpret_cast<float2*>(bank_dev), stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "prepare_bank launch");
+    return ok();
+}
+
+int fdas_correlate_sym_ex(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* bank_sym_dev,
+                          int K, int M, int L, float* plane_dev, int grid, hipStream_t stream)
+{
+    return correlate_impl(spec_dev, N, bank_sym_dev, K, M, L, plane_dev, grid, false, true,
+                          stream);
+}
+
+int fdas_correlate_sym(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* bank_sym_dev, int K,
+                       int M, int L, float* plane_dev, hipStream_t stream)
+{
+    return correlate_impl(spec_dev, N, bank_sym_dev, K, M, L, plane_dev, 0, false, true, stream);
 }
 
 size_t fdas_batched_workspace_bytes(int nspec)

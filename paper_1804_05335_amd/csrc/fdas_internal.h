@@ -19,9 +19,9 @@ hipError_t launch_prepare_bank(const float2* taps, int K, int M, int L, float2* 
 
 // Fused forward correlation of one spectrum on `grid` persistent workgroups
 // (0 = as many as the device holds resident); interbin selects the [K][2N]
-// interbinned plane.
+// interbinned plane, sym a bank holding only the z >= 0 rows.
 hipError_t launch_forward(const float2* spec, int64_t N, const float2* bank, int K, int M,
-                          int L, float* plane, int grid, bool interbin, hipStream_t s);
+                          int L, float* plane, int grid, bool interbin, bool sym, hipStream_t s);
 
 // Batched ragged correlation: segment scan into segpre[nspec + 1] (device
 // workspace), then the persistent kernel on `grid` workgroups (0 = fill the

@@ -129,6 +129,39 @@ struct Fwd {
             H[m] = h[T * m];
     }
 
+    // Symmetric bank (only the rows z >= 0, template index c = (K-1)/2 on):
+    // the row of template zi < c is the mirror of row c - zi, since
+    // T_{-z} = conj T_z gives H_{-z}[p] = conj H_z[(L - p) mod L].
+    __device__ static void load_row_sym(float2 (&H)[E], const float2* __restrict__ bank, int zi,
+                                        int c, int t)
+    {
+        if (zi >= c) {
+            load_row(H, bank, zi - c, t);
+        } else {
+            // position p = t + T m mirrors to (L - p) mod L: L - t - T m for
+            // m >= 1 (in (0, L) for every lane), and (L - t) mod L for m = 0
+            const float2* h = bank + (int64_t)(c - zi) * L;
+            const float2* hr = h + (L - t);
+            const float2 v0 = h[(L - t) & (L - 1)];
+            H[0] = make_float2(v0.x, -v0.y);
+#pragma unroll
+            for (int m = 1; m < E; ++m) {
+                const float2 v = hr[-T * m];
+                H[m] = make_float2(v.x, -v.y);
+            }
+        }
+    }
+
+    template <bool SYM>
+    __device__ static void load_bank_row(float2 (&H)[E], const float2* __restrict__ bank, int zi,
+                                         int K, int t)
+    {
+        if constexpr (SYM)
+            load_row_sym(H, bank, zi, (K - 1) / 2, t);
+        else
+            load_row(H, bank, zi, t);
+    }
+
     __device__ static void load_window(float2 (&X)[E], const float2* __restrict__ spec,
                                        int64_t N, int64_t in0, int t)
     {
@@ -150,7 +183,7 @@ struct Fwd {
     // y is staged through the LDS ping-pong buffer so each lane can read its
     // right-hand neighbour; the segment's spare valid output supplies y_{r+1}
     // for its last output.
-    template <bool IB>
+    template <bool IB, bool SYM = false>
     __device__ static void item(const float2* __restrict__ spec, int64_t N,
                                 const float2* __restrict__ bank, int K, int M, int64_t s, int z0,
                                 int z1, float* __restrict__ plane, const float2 (&tw)[NTW],
@@ -166,7 +199,7 @@ struct Fwd {
         for (int z = z0; z < z1; ++z) {
             float2 v[E];
             const int znext = z + 1 == K ? 0 : z + 1;
-            auto next = [&]() { load_row(H, bank, znext, t); };
+            auto next = [&]() { load_bank_row<SYM>(H, bank, znext, K, t); };
             if constexpr (!IB) {
                 F::template run_mul_hook<true, kMul>(X, H, v, la, lb, tw, t, next);
             } else {
@@ -237,8 +270,9 @@ __device__ __forceinline__ void item_range(int64_t total, int64_t& i0, int64_t& 
 }
 
 // One spectrum of N bins in nseg segments; persistent grid.  IB selects the
-// interbinned plane ([K][2N]) instead of the plain one ([K][N]).
-template <int L, bool IB>
+// interbinned plane ([K][2N]) instead of the plain one ([K][N]); SYM a bank
+// that stores only the z >= 0 rows.
+template <int L, bool IB, bool SYM>
 __global__ __launch_bounds__(Fwd<L>::T, 2) void forward_kernel(
     const float2* __restrict__ spec, int64_t N, const float2* __restrict__ bank, int K, int M,
     int64_t nseg, float* __restrict__ plane)
@@ -251,16 +285,17 @@ __global__ __launch_bounds__(Fwd<L>::T, 2) void forward_kernel(
         return;     // uniform across the workgroup, before any barrier
     const int t = threadIdx.x;
     float2 tw[W::NTW];
-    W::F::twiddles(tw, bank + (int64_t)K * L, t);
+    const int rows = SYM ? (K + 1) / 2 : K;      // bank rows before the twiddle row
+    W::F::twiddles(tw, bank + (int64_t)rows * L, t);
     float2* la = lds[0];
     float2* lb = lds[1];
     float2 H[W::E];
-    W::load_row(H, bank, (int)(i % K), t);
+    W::template load_bank_row<SYM>(H, bank, (int)(i % K), K, t);
     while (i < i1) {
         const int64_t s = i / K;
         const int zs = (int)(i - s * K);
         const int ze = (int)min<int64_t>(K, zs + (i1 - i));
-        W::template item<IB>(spec, N, bank, K, M, s, zs, ze, plane, tw, la, lb, t, H);
+        W::template item<IB, SYM>(spec, N, bank, K, M, s, zs, ze, plane, tw, la, lb, t, H);
         i += ze - zs;
     }
 }
@@ -561,44 +596,47 @@ static hipError_t resident_grid(Kern kernel, int threads, std::atomic<int>* cach
     return hipSuccess;
 }
 
-template <int L, bool IB>
+template <int L, bool IB, bool SYM>
 static hipError_t launch_forward_L(const float2* spec, int64_t N, const float2* bank, int K,
                                    int M, float* plane, int grid, hipStream_t s)
 {
     static std::atomic<int> cache[64];
     const int64_t nseg = (N + (L - M) - 1) / (L - M);
     if (grid <= 0) {
-        hipError_t e = resident_grid(forward_kernel<L, IB>, Fwd<L>::T, cache, &grid);
+        hipError_t e = resident_grid(forward_kernel<L, IB, SYM>, Fwd<L>::T, cache, &grid);
         if (e != hipSuccess)
             return e;
     }
     if ((int64_t)grid > nseg * K)
         grid = (int)(nseg * K);
-    hipLaunchKernelGGL((forward_kernel<L, IB>), dim3(grid), dim3(Fwd<L>::T), 0, s, spec, N,
+    hipLaunchKernelGGL((forward_kernel<L, IB, SYM>), dim3(grid), dim3(Fwd<L>::T), 0, s, spec, N,
                        bank, K, M, nseg, plane);
     return hipGetLastError();
 }
 
-template <bool IB>
+template <bool IB, bool SYM>
 static hipError_t launch_forward_ib(const float2* spec, int64_t N, const float2* bank, int K,
                                     int M, int L, float* plane, int grid, hipStream_t s)
 {
     switch (L) {
-    case 256:  return launch_forward_L<256, IB>(spec, N, bank, K, M, plane, grid, s);
-    case 512:  return launch_forward_L<512, IB>(spec, N, bank, K, M, plane, grid, s);
-    case 1024: return launch_forward_L<1024, IB>(spec, N, bank, K, M, plane, grid, s);
-    case 2048: return launch_forward_L<2048, IB>(spec, N, bank, K, M, plane, grid, s);
-    case 4096: return launch_forward_L<4096, IB>(spec, N, bank, K, M, plane, grid, s);
-    case 8192: return launch_forward_L<8192, IB>(spec, N, bank, K, M, plane, grid, s);
+    case 256:  return launch_forward_L<256, IB, SYM>(spec, N, bank, K, M, plane, grid, s);
+    case 512:  return launch_forward_L<512, IB, SYM>(spec, N, bank, K, M, plane, grid, s);
+    case 1024: return launch_forward_L<1024, IB, SYM>(spec, N, bank, K, M, plane, grid, s);
+    case 2048: return launch_forward_L<2048, IB, SYM>(spec, N, bank, K, M, plane, grid, s);
+    case 4096: return launch_forward_L<4096, IB, SYM>(spec, N, bank, K, M, plane, grid, s);
+    case 8192: return launch_forward_L<8192, IB, SYM>(spec, N, bank, K, M, plane, grid, s);
     default:   return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_forward(const float2* spec, int64_t N, const float2* bank, int K, int M,
-                          int L, float* plane, int grid, bool interbin, hipStream_t s)
+                          int L, float* plane, int grid, bool interbin, bool sym, hipStream_t s)
 {
-    return interbin ? launch_forward_ib<true>(spec, N, bank, K, M, L, plane, grid, s)
-                    : launch_forward_ib<false>(spec, N, bank, K, M, L, plane, grid, s);
+    if (sym)   // the symmetric bank serves the plain plane only
+        return interbin ? hipErrorInvalidValue
+                        : launch_forward_ib<false, true>(spec, N, bank, K, M, L, plane, grid, s);
+    return interbin ? launch_forward_ib<true, false>(spec, N, bank, K, M, L, plane, grid, s)
+                    : launch_forward_ib<false, false>(spec, N, bank, K, M, L, plane, grid, s);
 }
 
 template <int L>

@@ -181,3 +181,16 @@ def test_r2c_validation_before_any_device_call():
         _lib.FDAS_INVALID_ARG
     assert L.fdas_r2c(x, n, 1.0, spec, _fake(0x20000000 + 4096 * 256), wsb, None) == \
         _lib.FDAS_INVALID_ARG
+
+
+def test_symmetric_bank_validation():
+    L = _lib.lib()
+    assert L.fdas_bank_sym_elems(85, 2048) == 44 * 2048
+    assert L.fdas_bank_sym_elems(1, 512) == 2 * 512
+    for K in (0, 84, -1):
+        assert L.fdas_bank_sym_elems(K, 2048) == 0
+    p = _fake(0x10000)
+    assert L.fdas_prepare_bank_sym(p, 84, 256, 2048, p, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_correlate_sym(p, 1000, p, 84, 256, 2048, p, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_correlate_sym(p, 1000, p, 85, 255, 2048, p, None) == _lib.FDAS_UNSUPPORTED
+    assert L.fdas_correlate_sym_ex(p, 1000, p, 85, 256, 2048, p, -1, None) == _lib.FDAS_INVALID_ARG

@@ -180,3 +180,29 @@ def test_emulated_r2c_vs_oracle(emu, log2n):
     ref = r2c.spectrum(x, scale)
     assert np.max(np.abs(got - ref)) < TOL * np.max(np.abs(ref))
     assert np.linalg.norm(got - ref) < 1e-6 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("L,M,N,zmax", [(512, 64, 1500, 10.0), (2048, 256, 3900, 6.0),
+                                        (256, 2, 300, 0.0)])
+def test_emulated_symmetric_bank(emu, L, M, N, zmax):
+    # templates from the closed form (which has T_{-z} = conj T_z), the bank
+    # holding only z >= 0: the plane must match the full bank's and the oracle
+    taps = ot.templates(zmax, 2.0, M).astype(np.complex64)
+    K = taps.shape[0]
+    A = syn.random_spectrum(N + 11, N)
+    full = _bank(emu, taps, L)
+    emu.fdas_bank_sym_elems.restype = ctypes.c_int64
+    sym = np.zeros(emu.fdas_bank_sym_elems(K, L), dtype=np.complex64)
+    assert emu.fdas_prepare_bank_sym(_p(taps), K, M, L, _p(sym), None) == 0
+    c = (K - 1) // 2
+    assert np.array_equal(sym[:-L], full[c * L:K * L])       # rows z >= 0
+    assert np.array_equal(sym[-L:], full[K * L:])            # twiddle row
+    buf, plane = _guarded((K, N))
+    assert emu.fdas_correlate_sym_ex(_p(A), ctypes.c_int64(N), _p(sym), K, M, L, _p(plane), 0,
+                                     None) == 0
+    _check_guards(buf, plane)
+    ref = native.power(A, taps)
+    assert _rel(plane, ref) < TOL
+    one = np.zeros((K, N), dtype=np.float32)
+    assert emu.fdas_correlate(_p(A), ctypes.c_int64(N), _p(full), K, M, L, _p(one), None) == 0
+    assert _rel(plane, one) < TOL
