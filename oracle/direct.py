@@ -92,3 +92,31 @@ def interbinned_power(A, T) -> np.ndarray:
     P2[:, 0::2] = np.abs(Y[:, :N]) ** 2
     P2[:, 1::2] = np.abs((np.pi / 4) * (Y[:, :N] - Y[:, 1:N + 1])) ** 2
     return P2
+
+
+def fourier_interpolated_power(A, zmax: float, dz: float, M: int) -> np.ndarray:
+    """Two-bin Fourier interpolation (Sec. 3, the alternative to eq.
+    f-interp: templates and signal at doubled resolution), P2[K][2N]:
+    column 2r is |Y[r]|^2 with the M-tap templates, and column 2r+1 the
+    matched-filter response at the half bin r + 1/2 over the M bins centred
+    there, k in [r - M/2 + 1, r + M/2]:
+        Y_half[z][r] = sum_k A[k] conj(R(r + 1/2 - k, z)),
+    the spectrum zero outside [0, N).  Templates from the closed form."""
+    from . import templates as ot
+    A = np.asarray(A, dtype=np.complex128)
+    N = len(A)
+    T = ot.templates(zmax, dz, M)
+    zs = ot.z_grid(zmax, dz)
+    P2 = np.empty((len(zs), 2 * N), dtype=np.float64)
+    P2[:, 0::2] = power(A, T)
+    # k = r - M/2 + 1 + i, i in [0, M): offset q = r + 1/2 - k = M/2 - 1/2 - i
+    q = M / 2 - 0.5 - np.arange(M, dtype=np.float64)
+    pad = np.zeros(N + M, dtype=np.complex128)
+    pad[M // 2 - 1:M // 2 - 1 + N] = A            # pad[r + i] = A[r - M/2 + 1 + i]
+    for zi, z in enumerate(zs):
+        w = np.conj(ot.response(q, z))
+        Y = np.zeros(N, dtype=np.complex128)
+        for i in range(M):
+            Y += w[i] * pad[i:i + N]
+        P2[zi, 1::2] = Y.real ** 2 + Y.imag ** 2
+    return P2

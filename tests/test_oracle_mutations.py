@@ -175,7 +175,34 @@ def r2c_time_index_from_one(x):
     return r2c.dft(np.roll(np.asarray(x, dtype=np.float64), 1))
 
 
+def pin_fourier2(fi):
+    """Half-bin column of the two-bin interpolation: an accelerated signal at
+    k0 + 1/2 gives (sum over the window of |R(q, z0)|^2)^2, by quadrature."""
+    N, k0, M, z0 = 300, 150, 32, 8.0
+    A = ot.response(k0 + 0.5 - np.arange(N, dtype=np.float64), z0)
+    P2 = fi(A, 10.0, 2.0, M)
+    zi = int(np.argmin(np.abs(ot.z_grid(10.0, 2.0) - z0)))
+    q = M / 2 - 0.5 - np.arange(M, dtype=np.float64)
+    E = np.sum(np.abs(response_quadrature(q, z0)) ** 2)
+    return abs(P2[zi, 2 * k0 + 1] - E ** 2) < 1e-9
+
+
+def fourier2_reversed_offset(A, zmax, dz, M):
+    # the half-bin response taken at k - r - 1/2 instead of r + 1/2 - k
+    A = np.asarray(A, dtype=np.complex128)
+    return direct.fourier_interpolated_power(np.conj(A[::-1]), zmax, dz, M)[:, ::-1]
+
+
+def fourier2_window_off_by_one(A, zmax, dz, M):
+    A = np.asarray(A, dtype=np.complex128)
+    P2 = direct.fourier_interpolated_power(A, zmax, dz, M)
+    P2[:, 1::2] = np.roll(P2[:, 1::2], 1, axis=1)
+    return P2
+
+
 MUTANTS = {
+    "fourier2 offset sign": lambda: pin_fourier2(fourier2_reversed_offset),
+    "fourier2 window shift": lambda: pin_fourier2(fourier2_window_off_by_one),
     "r2c exponent sign": lambda: pin_r2c(r2c_wrong_exponent_sign),
     "r2c time origin": lambda: pin_r2c(r2c_time_index_from_one),
     "dropped conj": lambda: pin_chirp(_power_with(corr_dropped_conj), ot.templates),
@@ -205,6 +232,7 @@ def test_oracle_passes_every_pin():
     assert pin_half_bin(_ib(lambda y, yn, yp: np.abs((np.pi / 4) * (y - yn)) ** 2))
     assert pin_finite_differences(direct.grads)
     assert pin_r2c(r2c.dft)
+    assert pin_fourier2(direct.fourier_interpolated_power)
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
