@@ -328,9 +328,10 @@ def bench_workload5(fdas, torch, steps: int):
 
 
 def bench_interbin(fdas, torch, steps: int):
-    """Interbinned plane ([K][2N], eq. f-interp) against the plain plane on
-    the headline workload (2^21 bins, 85 x 256 taps, segment 2048); the
-    paper quotes interbinning at 1.1-1.6 times the plain run (Sec. 5)."""
+    """Interbinned plane ([K][2N], eq. f-interp) and the two-bin Fourier
+    interpolation (half-bin matched filter) against the plain plane on the
+    headline workload (2^21 bins, 85 x 256 taps, segment 2048); the paper
+    quotes interbinning at 1.1-1.6 times the plain run (Sec. 5)."""
     import fdas_synth as syn
     w = syn.workload(2)
     K, M, L = w.K, w.M, 2048
@@ -346,17 +347,25 @@ def bench_interbin(fdas, torch, steps: int):
     def ib():
         fdas.fdas_correlate_interbin(spec, N, bank, K, M, L, plane2)
 
-    for f in (plain, ib):
+    _, bank_h = fdas.make_bank_half(w.zmax, w.dz, M, L)
+
+    def fourier2():
+        fdas.fdas_correlate_fourier2(spec, N, bank, bank_h, K, M, L, plane2)
+
+    for f in (plain, ib, fourier2):
         for _ in range(5):
             f()
     ms_p = _timed(torch, plain, max(steps, 10))
     ms_i = _timed(torch, ib, max(steps, 10))
+    ms_f = _timed(torch, fourier2, max(steps, 10))
     bytes_i = 8 * N + 8 * K * N + 8 * K * L
     out = {"workload": f"2^21 bins, {K} templates x {M} taps, segment {L}",
            "plain_ms": ms_p, "interbinned_ms": ms_i, "interbinned_over_plain": ms_i / ms_p,
            "interbinned_points_per_s": 2 * K * N / ms_i * 1e3,
-           "interbinned_algorithmic_GB_per_s": bytes_i / ms_i / 1e6}
-    del spec, plane, plane2
+           "interbinned_algorithmic_GB_per_s": bytes_i / ms_i / 1e6,
+           "fourier2_ms": ms_f, "fourier2_over_plain": ms_f / ms_p,
+           "fourier2_points_per_s": 2 * K * N / ms_f * 1e3}
+    del spec, plane, plane2, bank_h
     torch.cuda.empty_cache()
     return out
 

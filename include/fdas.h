@@ -191,6 +191,35 @@ int fdas_correlate_sym(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf32 *ba
 int fdas_correlate_sym_ex(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf32 *bank_sym_dev,
                           int K, int M, int L, float *plane_dev, int grid, hipStream_t stream);
 
+/*
+ * Two-bin Fourier interpolation (Sec. 3: the more accurate alternative to
+ * interbinning, which doubles the template and signal resolution before the
+ * correlations).  Plane [K][2N] (plane2_dev, 8-byte aligned):
+ *     plane2[z][2r]   = |Y[z][r]|^2                     (the plain plane),
+ *     plane2[z][2r+1] = |sum_k A[k] conj(R(r + 1/2 - k, z))|^2,
+ * the half-bin matched filter over the M bins k in [r - M/2 + 1, r + M/2]
+ * (A zero outside [0, N)).  The half-bin sum is a correlation of the kind
+ * fdas_correlate computes, with M + 2 taps at offsets j - (M+2)/2 holding
+ * R(1/2 - offset, z) (taps 0 and 1 zero), so it runs on the same kernels
+ * with a second bank:
+ *
+ * fdas_make_templates_half: as fdas_make_templates for those K x (M + 2)
+ *   half-bin taps (taps_half_dev) and, if bank_half_dev is not NULL, their
+ *   bank for segment length L (fdas_bank_elems(K, L) values); needs
+ *   M + 2 <= L/2.  Synchronises the stream.
+ * fdas_correlate_fourier2(_ex): both planes into plane2_dev (two launches);
+ *   bank_dev from fdas_make_templates (M taps), bank_half_dev from
+ *   fdas_make_templates_half, same K and L.  Errors as fdas_correlate.
+ */
+int fdas_make_templates_half(double zmax, double dz, int M, int L, fdas_cf32 *taps_half_dev,
+                             fdas_cf32 *bank_half_dev, hipStream_t stream);
+int fdas_correlate_fourier2(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf32 *bank_dev,
+                            const fdas_cf32 *bank_half_dev, int K, int M, int L, float *plane2_dev,
+                            hipStream_t stream);
+int fdas_correlate_fourier2_ex(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf32 *bank_dev,
+                               const fdas_cf32 *bank_half_dev, int K, int M, int L,
+                               float *plane2_dev, int grid, hipStream_t stream);
+
 /* Bytes of device workspace fdas_correlate_batched needs for nspec spectra
  * (the per-spectrum segment prefix sums), rounded up to 256. */
 size_t fdas_batched_workspace_bytes(int nspec);

@@ -120,3 +120,21 @@ def fourier_interpolated_power(A, zmax: float, dz: float, M: int) -> np.ndarray:
             Y += w[i] * pad[i:i + N]
         P2[zi, 1::2] = Y.real ** 2 + Y.imag ** 2
     return P2
+
+
+def fourier_half_points(A, zmax: float, dz: float, M: int, zi, ri) -> np.ndarray:
+    """The half-bin column |Y_half[z][r]|^2 of fourier_interpolated_power at
+    the sampled (template index, bin) pairs, each from its defining sum."""
+    from . import templates as ot
+    A = np.asarray(A, dtype=np.complex128)
+    N = len(A)
+    zs = ot.z_grid(zmax, dz)
+    q = M / 2 - 0.5 - np.arange(M, dtype=np.float64)
+    W = np.conj(np.stack([ot.response(q, z) for z in zs]))          # [K][M]
+    pad = np.zeros(N + M, dtype=np.complex128)
+    pad[M // 2 - 1:M // 2 - 1 + N] = A
+    zi = np.asarray(zi, dtype=np.int64)
+    ri = np.asarray(ri, dtype=np.int64)
+    idx = ri[:, None] + np.arange(M)[None, :]
+    Y = np.sum(W[zi] * pad[idx], axis=1)
+    return Y.real ** 2 + Y.imag ** 2

@@ -18,7 +18,8 @@ from ._lib import (FdasError, fdas_backward_workspace_bytes, fdas_bank_elems,  #
                    fdas_make_templates_host, fdas_num_templates, fdas_prepare_bank,
                    fdas_r2c, fdas_r2c_workspace_bytes, fdas_template_response, fdas_version,
                    fdas_bank_sym_elems, fdas_correlate_sym, fdas_correlate_sym_ex,
-                   fdas_prepare_bank_sym, lib)
+                   fdas_prepare_bank_sym, fdas_make_templates_half, fdas_correlate_fourier2,
+                   fdas_correlate_fourier2_ex, lib)
 
 
 def make_bank(zmax: float, dz: float, M: int, L: int, device="cuda"):
@@ -127,3 +128,25 @@ def correlate_sym(spec, bank_sym, K: int, M: int, L: int, plane=None, grid: int 
         plane = torch.empty((K, N), dtype=torch.float32, device=spec.device)
     fdas_correlate_sym_ex(spec, N, bank_sym, K, M, L, plane, grid)
     return plane
+
+
+def make_bank_half(zmax: float, dz: float, M: int, L: int, device="cuda"):
+    """Half-bin templates (K x (M+2)) and their bank for the two-bin Fourier
+    interpolation."""
+    import torch
+    K = fdas_num_templates(zmax, dz)
+    taps = torch.empty(K * (M + 2), dtype=torch.complex64, device=device)
+    bank = torch.empty(fdas_bank_elems(K, L), dtype=torch.complex64, device=device)
+    fdas_make_templates_half(zmax, dz, M, L, taps, bank)
+    return taps.view(K, M + 2), bank
+
+
+def correlate_fourier2(spec, bank, bank_half, K: int, M: int, L: int, plane2=None, grid: int = 0):
+    """[K][2N] plane: integer bins in the even columns, the half-bin matched
+    filter in the odd ones."""
+    import torch
+    N = spec.numel()
+    if plane2 is None:
+        plane2 = torch.empty((K, 2 * N), dtype=torch.float32, device=spec.device)
+    fdas_correlate_fourier2_ex(spec, N, bank, bank_half, K, M, L, plane2, grid)
+    return plane2

@@ -54,6 +54,9 @@ SIGNATURES = [
     ("fdas_prepare_bank_sym", _I, [_P, _I, _I, _I, _P, _P]),
     ("fdas_correlate_sym", _I, [_P, _I64, _P, _I, _I, _I, _P, _P]),
     ("fdas_correlate_sym_ex", _I, [_P, _I64, _P, _I, _I, _I, _P, _I, _P]),
+    ("fdas_make_templates_half", _I, [_D, _D, _I, _I, _P, _P, _P]),
+    ("fdas_correlate_fourier2", _I, [_P, _I64, _P, _P, _I, _I, _I, _P, _P]),
+    ("fdas_correlate_fourier2_ex", _I, [_P, _I64, _P, _P, _I, _I, _I, _P, _I, _P]),
     ("fdas_r2c_workspace_bytes", _SZ, [_I64]),
     ("fdas_r2c", _I, [_P, _I64, ctypes.c_float, _P, _P, _SZ, _P]),
 ]
@@ -315,3 +318,31 @@ def fdas_correlate_sym_ex(spec, N: int, bank_sym, K: int, M: int, L: int, plane,
     _require(plane, torch.float32, "plane", K * N)
     _check(lib().fdas_correlate_sym_ex(_ptr(spec), N, _ptr(bank_sym), K, M, L, _ptr(plane), grid,
                                        _stream(stream, spec)), "fdas_correlate_sym")
+
+
+def fdas_make_templates_half(zmax: float, dz: float, M: int, L: int, taps_half, bank_half=None,
+                             stream=None) -> None:
+    import torch
+    K = fdas_num_templates(zmax, dz)
+    _require(taps_half, torch.complex64, "taps_half", K * (M + 2))
+    if bank_half is not None:
+        _require(bank_half, torch.complex64, "bank_half", fdas_bank_elems(K, L))
+    _check(lib().fdas_make_templates_half(zmax, dz, M, L, _ptr(taps_half), _ptr(bank_half),
+                                          _stream(stream, taps_half)), "fdas_make_templates_half")
+
+
+def fdas_correlate_fourier2(spec, N: int, bank, bank_half, K: int, M: int, L: int, plane2,
+                            stream=None) -> None:
+    fdas_correlate_fourier2_ex(spec, N, bank, bank_half, K, M, L, plane2, 0, stream)
+
+
+def fdas_correlate_fourier2_ex(spec, N: int, bank, bank_half, K: int, M: int, L: int, plane2,
+                               grid: int, stream=None) -> None:
+    import torch
+    _require(spec, torch.complex64, "spec", N)
+    _require(bank, torch.complex64, "bank", fdas_bank_elems(K, L))
+    _require(bank_half, torch.complex64, "bank_half", fdas_bank_elems(K, L))
+    _require(plane2, torch.float32, "plane2", 2 * K * N)
+    _check(lib().fdas_correlate_fourier2_ex(_ptr(spec), N, _ptr(bank), _ptr(bank_half), K, M, L,
+                                            _ptr(plane2), grid, _stream(stream, spec)),
+           "fdas_correlate_fourier2")

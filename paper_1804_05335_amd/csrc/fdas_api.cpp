@@ -83,6 +83,25 @@ void fill_templates(double dz, int K, int M, fdas_cf32* out)
     }
 }
 
+// Half-bin taps of the two-bin Fourier interpolation, K x (M + 2): tap j of
+// template z sits at bin offset j - (M+2)/2 and holds R(1/2 - offset, z) for
+// the M offsets -M/2+1 .. M/2 (the bins centred on the half bin); taps 0 and
+// 1 are zero.
+void fill_templates_half(double dz, int K, int M, fdas_cf32* out)
+{
+    const int Mh = M + 2;
+    for (int k = 0; k < K; ++k) {
+        const double z = (double(k) - 0.5 * double(K - 1)) * dz;
+        for (int j = 0; j < Mh; ++j) {
+            std::complex<double> r(0.0, 0.0);
+            if (j >= 2)
+                r = fdas::response(0.5 - double(j - Mh / 2), z);
+            out[(size_t)k * Mh + j].re = (float)r.real();
+            out[(size_t)k * Mh + j].im = (float)r.imag();
+        }
+    }
+}
+
 }  // namespace
 
 int fdas::fail_status(int status, const char* msg)
@@ -313,6 +332,85 @@ int fdas_correlate_sym(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* ba
                        int M, int L, float* plane_dev, hipStream_t stream)
 {
     return correlate_impl(spec_dev, N, bank_sym_dev, K, M, L, plane_dev, 0, false, true, stream);
+}
+
+int fdas_make_templates_half(double zmax, double dz, int M, int L, fdas_cf32* taps_half_dev,
+                             fdas_cf32* bank_half_dev, hipStream_t stream)
+{
+    int K = 0;
+    int st = check_grid(zmax, dz, &K);
+    if (st)
+        return st;
+    st = check_geometry(K, M + 2, L);
+    if (st)
+        return st;
+    if (M < 2 || (M & 1))
+        return fail(FDAS_UNSUPPORTED, "M = %d must be even and >= 2", M);
+    if (!taps_half_dev)
+        return fail(FDAS_INVALID_ARG, "taps_half_dev is NULL");
+    if (!aligned(taps_half_dev, 8) || (bank_half_dev && !aligned(bank_half_dev, 16)))
+        return fail(FDAS_INVALID_ARG, "taps_half_dev must be 8-byte and bank_half_dev 16-byte aligned");
+    std::vector<fdas_cf32> host;
+    try {
+        host.resize((size_t)K * (M + 2));
+    } catch (const std::bad_alloc&) {
+        return fail(FDAS_INVALID_ARG, "host allocation of %d x %d taps failed", K, M + 2);
+    }
+    fill_templates_half(dz, K, M, host.data());
+    hipError_t e = hipMemcpyAsync(taps_half_dev, host.data(), host.size() * sizeof(fdas_cf32),
+                                  hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "copy of half-bin taps to the device");
+    if (bank_half_dev) {
+        e = fdas::launch_prepare_bank(reinterpret_cast<const float2*>(taps_half_dev), K, M + 2, L,
+                                      reinterpret_cast<float2*>(bank_half_dev), stream);
+        if (e != hipSuccess)
+            return hip_fail(e, "prepare_bank launch");
+    }
+    e = hipStreamSynchronize(stream);   // the host copy must outlive the transfer
+    if (e != hipSuccess)
+        return hip_fail(e, "stream synchronize");
+    return ok();
+}
+
+int fdas_correlate_fourier2_ex(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* bank_dev,
+                               const fdas_cf32* bank_half_dev, int K, int M, int L,
+                               float* plane2_dev, int grid, hipStream_t stream)
+{
+    int st = check_geometry(K, M, L);
+    if (st)
+        return st;
+    st = check_geometry(K, M + 2, L);
+    if (st)
+        return st;
+    if (N < 0 || N > kMaxN)
+        return fail(FDAS_INVALID_ARG, "N = %lld outside [0, 2^32]", (long long)N);
+    if (grid < 0 || grid > kMaxGrid)
+        return fail(FDAS_INVALID_ARG, "grid = %d outside [0, %d]", grid, kMaxGrid);
+    if (N == 0)
+        return ok();
+    if (!spec_dev || !bank_dev || !bank_half_dev || !plane2_dev)
+        return fail(FDAS_INVALID_ARG, "spec, bank, bank_half and plane2 must not be NULL");
+    if (!aligned(spec_dev, 8) || !aligned(bank_dev, 16) || !aligned(bank_half_dev, 16) ||
+        !aligned(plane2_dev, 8))
+        return fail(FDAS_INVALID_ARG, "misaligned pointer (spec 8 B, banks 16 B, plane2 8 B)");
+    const auto* spec = reinterpret_cast<const float2*>(spec_dev);
+    hipError_t e = fdas::launch_forward_column(spec, N, reinterpret_cast<const float2*>(bank_dev),
+                                               K, M, L, plane2_dev, 0, grid, stream);
+    if (e == hipSuccess)
+        e = fdas::launch_forward_column(spec, N, reinterpret_cast<const float2*>(bank_half_dev),
+                                        K, M + 2, L, plane2_dev, 1, grid, stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "forward launch");
+    return ok();
+}
+
+int fdas_correlate_fourier2(const fdas_cf32* spec_dev, int64_t N, const fdas_cf32* bank_dev,
+                            const fdas_cf32* bank_half_dev, int K, int M, int L, float* plane2_dev,
+                            hipStream_t stream)
+{
+    return fdas_correlate_fourier2_ex(spec_dev, N, bank_dev, bank_half_dev, K, M, L, plane2_dev, 0,
+                                      stream);
 }
 
 size_t fdas_batched_workspace_bytes(int nspec)

@@ -23,6 +23,10 @@ hipError_t launch_prepare_bank(const float2* taps, int K, int M, int L, float2* 
 hipError_t launch_forward(const float2* spec, int64_t N, const float2* bank, int K, int M,
                           int L, float* plane, int grid, bool interbin, bool sym, hipStream_t s);
 
+// The plain powers written to column 2r + col (col 0 or 1) of a [K][2N] plane.
+hipError_t launch_forward_column(const float2* spec, int64_t N, const float2* bank, int K, int M,
+                                 int L, float* plane2, int col, int grid, hipStream_t s);
+
 // Batched ragged correlation: segment scan into segpre[nspec + 1] (device
 // workspace), then the persistent kernel on `grid` workgroups (0 = fill the
 // device at full occupancy).

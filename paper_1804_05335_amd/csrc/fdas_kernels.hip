@@ -183,11 +183,15 @@ struct Fwd {
     // y is staged through the LDS ping-pong buffer so each lane can read its
     // right-hand neighbour; the segment's spare valid output supplies y_{r+1}
     // for its last output.
-    template <bool IB, bool SYM = false>
+    //
+    // HALF: the plain powers go to column 2r + col of a [K][2N] plane (the
+    // two-bin Fourier interpolation writes its integer and half-bin planes
+    // interleaved this way).
+    template <bool IB, bool SYM = false, bool HALF = false>
     __device__ static void item(const float2* __restrict__ spec, int64_t N,
                                 const float2* __restrict__ bank, int K, int M, int64_t s, int z0,
                                 int z1, float* __restrict__ plane, const float2 (&tw)[NTW],
-                                float2*& la, float2*& lb, int t, float2 (&H)[E])
+                                float2*& la, float2*& lb, int t, float2 (&H)[E], int col = 0)
     {
         const int B = L - M;
         const int64_t out0 = s * B;
@@ -210,13 +214,14 @@ struct Fwd {
                 F::template run_mul_hook<true, kMul>(X, H, v, la, lb, tw, t, none);
             }
             if constexpr (!IB) {
-                const float* row_q0 = plane + ((int64_t)z * N + out0 - M / 2);
-                const auto rs = seg_rsrc(row_q0, (M / 2 + nvalid) * 4);
+                constexpr int S = HALF ? 2 : 1;             // plane columns per output
+                const float* row_q0 = plane + (S * ((int64_t)z * N + out0 - M / 2) + col);
+                const auto rs = seg_rsrc(row_q0, (M / 2 + nvalid) * 4 * S);
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const float p = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
                     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(p), rs,
-                                                          seg_off<4>(t + T * m, M / 2), 0,
+                                                          seg_off<4 * S>(t + T * m, M / 2), 0,
                                                           kNonTemporal);
                 }
             } else {
@@ -271,11 +276,12 @@ __device__ __forceinline__ void item_range(int64_t total, int64_t& i0, int64_t& 
 
 // One spectrum of N bins in nseg segments; persistent grid.  IB selects the
 // interbinned plane ([K][2N]) instead of the plain one ([K][N]); SYM a bank
-// that stores only the z >= 0 rows.
-template <int L, bool IB, bool SYM>
+// that stores only the z >= 0 rows; HALF writes column 2r + col of a [K][2N]
+// plane.
+template <int L, bool IB, bool SYM, bool HALF>
 __global__ __launch_bounds__(Fwd<L>::T, 2) void forward_kernel(
     const float2* __restrict__ spec, int64_t N, const float2* __restrict__ bank, int K, int M,
-    int64_t nseg, float* __restrict__ plane)
+    int64_t nseg, float* __restrict__ plane, int col)
 {
     using W = Fwd<L>;
     __shared__ float2 lds[2][LdsSize<L>::value];
@@ -295,7 +301,8 @@ __global__ __launch_bounds__(Fwd<L>::T, 2) void forward_kernel(
         const int64_t s = i / K;
         const int zs = (int)(i - s * K);
         const int ze = (int)min<int64_t>(K, zs + (i1 - i));
-        W::template item<IB, SYM>(spec, N, bank, K, M, s, zs, ze, plane, tw, la, lb, t, H);
+        W::template item<IB, SYM, HALF>(spec, N, bank, K, M, s, zs, ze, plane, tw, la, lb, t, H,
+                                         col);
         i += ze - zs;
     }
 }
@@ -596,35 +603,35 @@ static hipError_t resident_grid(Kern kernel, int threads, std::atomic<int>* cach
     return hipSuccess;
 }
 
-template <int L, bool IB, bool SYM>
+template <int L, bool IB, bool SYM, bool HALF>
 static hipError_t launch_forward_L(const float2* spec, int64_t N, const float2* bank, int K,
-                                   int M, float* plane, int grid, hipStream_t s)
+                                   int M, float* plane, int grid, int col, hipStream_t s)
 {
     static std::atomic<int> cache[64];
     const int64_t nseg = (N + (L - M) - 1) / (L - M);
     if (grid <= 0) {
-        hipError_t e = resident_grid(forward_kernel<L, IB, SYM>, Fwd<L>::T, cache, &grid);
+        hipError_t e = resident_grid(forward_kernel<L, IB, SYM, HALF>, Fwd<L>::T, cache, &grid);
         if (e != hipSuccess)
             return e;
     }
     if ((int64_t)grid > nseg * K)
         grid = (int)(nseg * K);
-    hipLaunchKernelGGL((forward_kernel<L, IB, SYM>), dim3(grid), dim3(Fwd<L>::T), 0, s, spec, N,
-                       bank, K, M, nseg, plane);
+    hipLaunchKernelGGL((forward_kernel<L, IB, SYM, HALF>), dim3(grid), dim3(Fwd<L>::T), 0, s,
+                       spec, N, bank, K, M, nseg, plane, col);
     return hipGetLastError();
 }
 
-template <bool IB, bool SYM>
+template <bool IB, bool SYM, bool HALF>
 static hipError_t launch_forward_ib(const float2* spec, int64_t N, const float2* bank, int K,
-                                    int M, int L, float* plane, int grid, hipStream_t s)
+                                    int M, int L, float* plane, int grid, int col, hipStream_t s)
 {
     switch (L) {
-    case 256:  return launch_forward_L<256, IB, SYM>(spec, N, bank, K, M, plane, grid, s);
-    case 512:  return launch_forward_L<512, IB, SYM>(spec, N, bank, K, M, plane, grid, s);
-    case 1024: return launch_forward_L<1024, IB, SYM>(spec, N, bank, K, M, plane, grid, s);
-    case 2048: return launch_forward_L<2048, IB, SYM>(spec, N, bank, K, M, plane, grid, s);
-    case 4096: return launch_forward_L<4096, IB, SYM>(spec, N, bank, K, M, plane, grid, s);
-    case 8192: return launch_forward_L<8192, IB, SYM>(spec, N, bank, K, M, plane, grid, s);
+    case 256:  return launch_forward_L<256, IB, SYM, HALF>(spec, N, bank, K, M, plane, grid, col, s);
+    case 512:  return launch_forward_L<512, IB, SYM, HALF>(spec, N, bank, K, M, plane, grid, col, s);
+    case 1024: return launch_forward_L<1024, IB, SYM, HALF>(spec, N, bank, K, M, plane, grid, col, s);
+    case 2048: return launch_forward_L<2048, IB, SYM, HALF>(spec, N, bank, K, M, plane, grid, col, s);
+    case 4096: return launch_forward_L<4096, IB, SYM, HALF>(spec, N, bank, K, M, plane, grid, col, s);
+    case 8192: return launch_forward_L<8192, IB, SYM, HALF>(spec, N, bank, K, M, plane, grid, col, s);
     default:   return hipErrorInvalidValue;
     }
 }
@@ -634,9 +641,17 @@ hipError_t launch_forward(const float2* spec, int64_t N, const float2* bank, int
 {
     if (sym)   // the symmetric bank serves the plain plane only
         return interbin ? hipErrorInvalidValue
-                        : launch_forward_ib<false, true>(spec, N, bank, K, M, L, plane, grid, s);
-    return interbin ? launch_forward_ib<true, false>(spec, N, bank, K, M, L, plane, grid, s)
-                    : launch_forward_ib<false, false>(spec, N, bank, K, M, L, plane, grid, s);
+                        : launch_forward_ib<false, true, false>(spec, N, bank, K, M, L, plane,
+                                                                grid, 0, s);
+    return interbin
+               ? launch_forward_ib<true, false, false>(spec, N, bank, K, M, L, plane, grid, 0, s)
+               : launch_forward_ib<false, false, false>(spec, N, bank, K, M, L, plane, grid, 0, s);
+}
+
+hipError_t launch_forward_column(const float2* spec, int64_t N, const float2* bank, int K, int M,
+                                 int L, float* plane2, int col, int grid, hipStream_t s)
+{
+    return launch_forward_ib<false, false, true>(spec, N, bank, K, M, L, plane2, grid, col, s);
 }
 
 template <int L>

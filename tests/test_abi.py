@@ -194,3 +194,19 @@ def test_symmetric_bank_validation():
     assert L.fdas_correlate_sym(p, 1000, p, 84, 256, 2048, p, None) == _lib.FDAS_INVALID_ARG
     assert L.fdas_correlate_sym(p, 1000, p, 85, 255, 2048, p, None) == _lib.FDAS_UNSUPPORTED
     assert L.fdas_correlate_sym_ex(p, 1000, p, 85, 256, 2048, p, -1, None) == _lib.FDAS_INVALID_ARG
+
+
+def test_fourier2_validation_before_any_device_call():
+    L = _lib.lib()
+    p = _fake(0x10000)
+    # M + 2 must fit L/2
+    assert L.fdas_make_templates_half(ctypes.c_double(84.0), ctypes.c_double(2.0), 1024, 2048, p,
+                                      p, None) == _lib.FDAS_UNSUPPORTED
+    assert L.fdas_correlate_fourier2(p, 1000, p, p, 85, 1024, 2048, p, None) == \
+        _lib.FDAS_UNSUPPORTED
+    assert L.fdas_correlate_fourier2(p, 1000, p, p, 85, 256, 2048, _fake(0x10004), None) == \
+        _lib.FDAS_INVALID_ARG
+    assert L.fdas_correlate_fourier2(p, 1000, p, None, 85, 256, 2048, p, None) == \
+        _lib.FDAS_INVALID_ARG
+    assert L.fdas_correlate_fourier2_ex(p, 1000, p, p, 85, 256, 2048, p, -3, None) == \
+        _lib.FDAS_INVALID_ARG

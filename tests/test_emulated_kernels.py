@@ -206,3 +206,23 @@ def test_emulated_symmetric_bank(emu, L, M, N, zmax):
     one = np.zeros((K, N), dtype=np.float32)
     assert emu.fdas_correlate(_p(A), ctypes.c_int64(N), _p(full), K, M, L, _p(one), None) == 0
     assert _rel(plane, one) < TOL
+
+
+@pytest.mark.parametrize("L,M,N,zmax", [(512, 64, 1500, 10.0), (2048, 256, 3900, 6.0),
+                                        (256, 2, 300, 2.0), (1024, 126, 777, 4.0)])
+def test_emulated_fourier2(emu, L, M, N, zmax):
+    from oracle import direct
+    A = syn.random_spectrum(N + 23, N)
+    taps = ot.templates(zmax, 2.0, M).astype(np.complex64)
+    K = taps.shape[0]
+    bank = _bank(emu, taps, L)
+    taps_h = np.zeros(K * (M + 2), dtype=np.complex64)
+    bank_h = np.zeros((K + 1) * L, dtype=np.complex64)
+    assert emu.fdas_make_templates_half(ctypes.c_double(zmax), ctypes.c_double(2.0), M, L,
+                                        _p(taps_h), _p(bank_h), None) == 0
+    buf, plane2 = _guarded((K, 2 * N))
+    assert emu.fdas_correlate_fourier2_ex(_p(A), ctypes.c_int64(N), _p(bank), _p(bank_h), K, M, L,
+                                          _p(plane2), 0, None) == 0
+    _check_guards(buf, plane2)
+    ref = direct.fourier_interpolated_power(A, zmax, 2.0, M)
+    assert _rel(plane2, ref) < TOL

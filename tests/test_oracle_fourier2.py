@@ -65,3 +65,13 @@ def test_time_domain_chirp_at_a_half_bin():
     zz, cc = np.unravel_index(np.argmax(P2), P2.shape)
     assert ot.z_grid(20.0, 2.0)[zz] == z0 and cc == 2 * 3000 + 1
     assert abs(P2[zz, cc] / 50.0 - 1.0) < 1e-2
+
+
+def test_points_match_full_plane():
+    A = syn.random_spectrum(8, 700).astype(np.complex128)
+    P2 = direct.fourier_interpolated_power(A, 10.0, 2.0, 64)
+    rng = np.random.default_rng(2)
+    zi = rng.integers(0, P2.shape[0], 500)
+    ri = np.concatenate([rng.integers(0, 700, 494), [0, 1, 2, 697, 698, 699]])
+    got = direct.fourier_half_points(A, 10.0, 2.0, 64, zi, ri)
+    assert np.max(np.abs(got - P2[zi, 2 * ri + 1])) < 1e-12 * np.max(P2)
