@@ -207,9 +207,11 @@ int fdas_correlate_sym_ex(const fdas_cf32 *spec_dev, int64_t N, const fdas_cf32 
  *   half-bin taps (taps_half_dev) and, if bank_half_dev is not NULL, their
  *   bank for segment length L (fdas_bank_elems(K, L) values); needs
  *   M + 2 <= L/2.  Synchronises the stream.
- * fdas_correlate_fourier2(_ex): both planes into plane2_dev (two launches);
- *   bank_dev from fdas_make_templates (M taps), bank_half_dev from
- *   fdas_make_templates_half, same K and L.  Errors as fdas_correlate.
+ * fdas_correlate_fourier2(_ex): both planes into plane2_dev in one launch
+ *   (both inverse transforms per template on a shared segment FFT, segments
+ *   of B = L - M - 2 outputs); bank_dev from fdas_make_templates (M taps),
+ *   bank_half_dev from fdas_make_templates_half, same K and L.  Errors as
+ *   fdas_correlate.
  */
 int fdas_make_templates_half(double zmax, double dz, int M, int L, fdas_cf32 *taps_half_dev,
                              fdas_cf32 *bank_half_dev, hipStream_t stream);

@@ -394,12 +394,11 @@ int fdas_correlate_fourier2_ex(const fdas_cf32* spec_dev, int64_t N, const fdas_
     if (!aligned(spec_dev, 8) || !aligned(bank_dev, 16) || !aligned(bank_half_dev, 16) ||
         !aligned(plane2_dev, 8))
         return fail(FDAS_INVALID_ARG, "misaligned pointer (spec 8 B, banks 16 B, plane2 8 B)");
-    const auto* spec = reinterpret_cast<const float2*>(spec_dev);
-    hipError_t e = fdas::launch_forward_column(spec, N, reinterpret_cast<const float2*>(bank_dev),
-                                               K, M, L, plane2_dev, 0, grid, stream);
-    if (e == hipSuccess)
-        e = fdas::launch_forward_column(spec, N, reinterpret_cast<const float2*>(bank_half_dev),
-                                        K, M + 2, L, plane2_dev, 1, grid, stream);
+    // the M-tap bank places its taps exactly where the same taps zero-padded
+    // to M + 2 would go, so both banks run on the (M + 2)-tap geometry
+    hipError_t e = fdas::launch_forward_dual(
+        reinterpret_cast<const float2*>(spec_dev), N, reinterpret_cast<const float2*>(bank_dev),
+        reinterpret_cast<const float2*>(bank_half_dev), K, M + 2, L, plane2_dev, grid, stream);
     if (e != hipSuccess)
         return hip_fail(e, "forward launch");
     return ok();

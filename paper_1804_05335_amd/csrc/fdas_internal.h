@@ -23,9 +23,12 @@ hipError_t launch_prepare_bank(const float2* taps, int K, int M, int L, float2* 
 hipError_t launch_forward(const float2* spec, int64_t N, const float2* bank, int K, int M,
                           int L, float* plane, int grid, bool interbin, bool sym, hipStream_t s);
 
-// The plain powers written to column 2r + col (col 0 or 1) of a [K][2N] plane.
-hipError_t launch_forward_column(const float2* spec, int64_t N, const float2* bank, int K, int M,
-                                 int L, float* plane2, int col, int grid, hipStream_t s);
+// Two-bin Fourier interpolation: the integer bank and the half-bin bank on
+// one segment geometry of Mgeom taps (the half-bin tap count, M + 2), both
+// inverse transforms per template, pairs written into the [K][2N] plane.
+hipError_t launch_forward_dual(const float2* spec, int64_t N, const float2* bank,
+                               const float2* bank_half, int K, int Mgeom, int L, float* plane2,
+                               int grid, hipStream_t s);
 
 // Batched ragged correlation: segment scan into segpre[nspec + 1] (device
 // workspace), then the persistent kernel on `grid` workgroups (0 = fill the

@@ -184,14 +184,17 @@ struct Fwd {
     // right-hand neighbour; the segment's spare valid output supplies y_{r+1}
     // for its last output.
     //
-    // HALF: the plain powers go to column 2r + col of a [K][2N] plane (the
-    // two-bin Fourier interpolation writes its integer and half-bin planes
-    // interleaved this way).
-    template <bool IB, bool SYM = false, bool HALF = false>
+    // DUAL (two-bin Fourier interpolation): bank2 holds the half-bin
+    // filters on the same segment geometry; per template both inverse
+    // transforms run on the window's X (the half-bin row is loaded as soon
+    // as the first has consumed the integer row) and the [K][2N] plane gets
+    // the pair (|y_r|^2, |y_half_r|^2) in one 8-byte store.
+    template <bool IB, bool SYM = false, bool DUAL = false>
     __device__ static void item(const float2* __restrict__ spec, int64_t N,
                                 const float2* __restrict__ bank, int K, int M, int64_t s, int z0,
                                 int z1, float* __restrict__ plane, const float2 (&tw)[NTW],
-                                float2*& la, float2*& lb, int t, float2 (&H)[E], int col = 0)
+                                float2*& la, float2*& lb, int t, float2 (&H)[E],
+                                const float2* __restrict__ bank2 = nullptr)
     {
         const int B = L - M;
         const int64_t out0 = s * B;
@@ -204,6 +207,25 @@ struct Fwd {
             float2 v[E];
             const int znext = z + 1 == K ? 0 : z + 1;
             auto next = [&]() { load_bank_row<SYM>(H, bank, znext, K, t); };
+            if constexpr (DUAL) {
+                auto half = [&]() { load_row(H, bank2, z, t); };
+                F::template run_mul_hook<true, kMul>(X, H, v, la, lb, tw, t, half);
+                float p1[E];
+#pragma unroll
+                for (int m = 0; m < E; ++m)
+                    p1[m] = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
+                F::template run_mul_hook<true, kMul>(X, H, v, la, lb, tw, t, next);
+                const float* row_q0 = plane + 2 * ((int64_t)z * N + out0 - M / 2);
+                const auto rs = seg_rsrc(row_q0, (M / 2 + nvalid) * 8);
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const float p2 = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
+                    const u32x2 pp = {__float_as_uint(p1[m]), __float_as_uint(p2)};
+                    __builtin_amdgcn_raw_buffer_store_b64(pp, rs, seg_off<8>(t + T * m, M / 2), 0,
+                                                          kNonTemporal);
+                }
+                continue;
+            }
             if constexpr (!IB) {
                 F::template run_mul_hook<true, kMul>(X, H, v, la, lb, tw, t, next);
             } else {
@@ -214,14 +236,13 @@ struct Fwd {
                 F::template run_mul_hook<true, kMul>(X, H, v, la, lb, tw, t, none);
             }
             if constexpr (!IB) {
-                constexpr int S = HALF ? 2 : 1;             // plane columns per output
-                const float* row_q0 = plane + (S * ((int64_t)z * N + out0 - M / 2) + col);
-                const auto rs = seg_rsrc(row_q0, (M / 2 + nvalid) * 4 * S);
+                const float* row_q0 = plane + ((int64_t)z * N + out0 - M / 2);
+                const auto rs = seg_rsrc(row_q0, (M / 2 + nvalid) * 4);
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const float p = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
                     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(p), rs,
-                                                          seg_off<4 * S>(t + T * m, M / 2), 0,
+                                                          seg_off<4>(t + T * m, M / 2), 0,
                                                           kNonTemporal);
                 }
             } else {
@@ -276,12 +297,12 @@ __device__ __forceinline__ void item_range(int64_t total, int64_t& i0, int64_t& 
 
 // One spectrum of N bins in nseg segments; persistent grid.  IB selects the
 // interbinned plane ([K][2N]) instead of the plain one ([K][N]); SYM a bank
-// that stores only the z >= 0 rows; HALF writes column 2r + col of a [K][2N]
-// plane.
-template <int L, bool IB, bool SYM, bool HALF>
+// that stores only the z >= 0 rows; DUAL adds the half-bin bank bank2 and
+// writes interleaved [K][2N] pairs.
+template <int L, bool IB, bool SYM, bool DUAL>
 __global__ __launch_bounds__(Fwd<L>::T, 2) void forward_kernel(
     const float2* __restrict__ spec, int64_t N, const float2* __restrict__ bank, int K, int M,
-    int64_t nseg, float* __restrict__ plane, int col)
+    int64_t nseg, float* __restrict__ plane, const float2* __restrict__ bank2)
 {
     using W = Fwd<L>;
     __shared__ float2 lds[2][LdsSize<L>::value];
@@ -301,8 +322,8 @@ __global__ __launch_bounds__(Fwd<L>::T, 2) void forward_kernel(
         const int64_t s = i / K;
         const int zs = (int)(i - s * K);
         const int ze = (int)min<int64_t>(K, zs + (i1 - i));
-        W::template item<IB, SYM, HALF>(spec, N, bank, K, M, s, zs, ze, plane, tw, la, lb, t, H,
-                                         col);
+        W::template item<IB, SYM, DUAL>(spec, N, bank, K, M, s, zs, ze, plane, tw, la, lb, t, H,
+                                         bank2);
         i += ze - zs;
     }
 }
@@ -603,35 +624,37 @@ static hipError_t resident_grid(Kern kernel, int threads, std::atomic<int>* cach
     return hipSuccess;
 }
 
-template <int L, bool IB, bool SYM, bool HALF>
+template <int L, bool IB, bool SYM, bool DUAL>
 static hipError_t launch_forward_L(const float2* spec, int64_t N, const float2* bank, int K,
-                                   int M, float* plane, int grid, int col, hipStream_t s)
+                                   int M, float* plane, int grid, const float2* bank2,
+                                   hipStream_t s)
 {
     static std::atomic<int> cache[64];
     const int64_t nseg = (N + (L - M) - 1) / (L - M);
     if (grid <= 0) {
-        hipError_t e = resident_grid(forward_kernel<L, IB, SYM, HALF>, Fwd<L>::T, cache, &grid);
+        hipError_t e = resident_grid(forward_kernel<L, IB, SYM, DUAL>, Fwd<L>::T, cache, &grid);
         if (e != hipSuccess)
             return e;
     }
     if ((int64_t)grid > nseg * K)
         grid = (int)(nseg * K);
-    hipLaunchKernelGGL((forward_kernel<L, IB, SYM, HALF>), dim3(grid), dim3(Fwd<L>::T), 0, s,
-                       spec, N, bank, K, M, nseg, plane, col);
+    hipLaunchKernelGGL((forward_kernel<L, IB, SYM, DUAL>), dim3(grid), dim3(Fwd<L>::T), 0, s,
+                       spec, N, bank, K, M, nseg, plane, bank2);
     return hipGetLastError();
 }
 
-template <bool IB, bool SYM, bool HALF>
+template <bool IB, bool SYM, bool DUAL>
 static hipError_t launch_forward_ib(const float2* spec, int64_t N, const float2* bank, int K,
-                                    int M, int L, float* plane, int grid, int col, hipStream_t s)
+                                    int M, int L, float* plane, int grid, const float2* bank2,
+                                    hipStream_t s)
 {
     switch (L) {
-    case 256:  return launch_forward_L<256, IB, SYM, HALF>(spec, N, bank, K, M, plane, grid, col, s);
-    case 512:  return launch_forward_L<512, IB, SYM, HALF>(spec, N, bank, K, M, plane, grid, col, s);
-    case 1024: return launch_forward_L<1024, IB, SYM, HALF>(spec, N, bank, K, M, plane, grid, col, s);
-    case 2048: return launch_forward_L<2048, IB, SYM, HALF>(spec, N, bank, K, M, plane, grid, col, s);
-    case 4096: return launch_forward_L<4096, IB, SYM, HALF>(spec, N, bank, K, M, plane, grid, col, s);
-    case 8192: return launch_forward_L<8192, IB, SYM, HALF>(spec, N, bank, K, M, plane, grid, col, s);
+    case 256:  return launch_forward_L<256, IB, SYM, DUAL>(spec, N, bank, K, M, plane, grid, bank2, s);
+    case 512:  return launch_forward_L<512, IB, SYM, DUAL>(spec, N, bank, K, M, plane, grid, bank2, s);
+    case 1024: return launch_forward_L<1024, IB, SYM, DUAL>(spec, N, bank, K, M, plane, grid, bank2, s);
+    case 2048: return launch_forward_L<2048, IB, SYM, DUAL>(spec, N, bank, K, M, plane, grid, bank2, s);
+    case 4096: return launch_forward_L<4096, IB, SYM, DUAL>(spec, N, bank, K, M, plane, grid, bank2, s);
+    case 8192: return launch_forward_L<8192, IB, SYM, DUAL>(spec, N, bank, K, M, plane, grid, bank2, s);
     default:   return hipErrorInvalidValue;
     }
 }
@@ -642,16 +665,20 @@ hipError_t launch_forward(const float2* spec, int64_t N, const float2* bank, int
     if (sym)   // the symmetric bank serves the plain plane only
         return interbin ? hipErrorInvalidValue
                         : launch_forward_ib<false, true, false>(spec, N, bank, K, M, L, plane,
-                                                                grid, 0, s);
+                                                                grid, nullptr, s);
     return interbin
-               ? launch_forward_ib<true, false, false>(spec, N, bank, K, M, L, plane, grid, 0, s)
-               : launch_forward_ib<false, false, false>(spec, N, bank, K, M, L, plane, grid, 0, s);
+               ? launch_forward_ib<true, false, false>(spec, N, bank, K, M, L, plane, grid,
+                                                       nullptr, s)
+               : launch_forward_ib<false, false, false>(spec, N, bank, K, M, L, plane, grid,
+                                                        nullptr, s);
 }
 
-hipError_t launch_forward_column(const float2* spec, int64_t N, const float2* bank, int K, int M,
-                                 int L, float* plane2, int col, int grid, hipStream_t s)
+hipError_t launch_forward_dual(const float2* spec, int64_t N, const float2* bank,
+                               const float2* bank_half, int K, int Mgeom, int L, float* plane2,
+                               int grid, hipStream_t s)
 {
-    return launch_forward_ib<false, false, true>(spec, N, bank, K, M, L, plane2, grid, col, s);
+    return launch_forward_ib<false, false, true>(spec, N, bank, K, Mgeom, L, plane2, grid,
+                                                 bank_half, s);
 }
 
 template <int L>
