@@ -2,7 +2,7 @@
 matched filter, templates and signal at doubled resolution) against the FP64
 oracle: full planes at the 2^16-bin workload for every segment length,
 sampled integer and half-bin columns at the 2^21-bin / 85-template workload,
-and bitwise agreement of the integer columns with the plain plane."""
+and agreement of the integer columns with the plain plane."""
 import numpy as np
 import pytest
 
@@ -38,8 +38,10 @@ def test_fourier2_full_plane_workload1(fd, L):
     P2 = fd.correlate_fourier2(spec, bank, bank_h, K, w.M, L).cpu().numpy()
     ref = direct.fourier_interpolated_power(w.spectra[0], w.zmax, w.dz, w.M)
     assert _rel(P2, ref) < TOL
+    # the integer columns come from the (M + 2)-tap segment tiling shared
+    # with the half-bin bank: the plain plane up to FP32 rounding
     plain = fd.correlate(spec, bank, K, w.M, L).cpu().numpy()
-    assert np.array_equal(P2[:, 0::2], plain)
+    assert _rel(P2[:, 0::2], plain.astype(np.float64)) < TOL
 
 
 def test_fourier2_workload2_sampled(fd):
