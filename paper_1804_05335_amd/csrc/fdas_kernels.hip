@@ -13,10 +13,6 @@ namespace fdas {
 
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
-#ifndef FDAS_IB_GROUP
-#define FDAS_IB_GROUP 4
-#endif
-constexpr int kIbGroup = FDAS_IB_GROUP;
 
 // ---- range-checked segment access ---------------------------------------------
 //
@@ -180,9 +176,8 @@ struct Fwd {
     //
     // IB (interbinning, Sec. 3 eq. f-interp): the plane has 2N columns per
     // row; column 2r holds |y_r|^2 and column 2r+1 |(pi/4)(y_r - y_{r+1})|^2.
-    // y is staged through the LDS ping-pong buffer so each lane can read its
-    // right-hand neighbour; the segment's spare valid output supplies y_{r+1}
-    // for its last output.
+    // Each lane gets its right-hand neighbour's y by a lane rotation; the
+    // segment's spare valid output supplies y_{r+1} for its last output.
     //
     // DUAL (two-bin Fourier interpolation): bank2 holds the half-bin
     // filters on the same segment geometry; per template both inverse
@@ -246,35 +241,45 @@ struct Fwd {
                                                           kNonTemporal);
                 }
             } else {
+                // y at q + 1 = (t + 1) + T m is lane t + 1's v[m]: a lane
+                // rotation within the wave (ds_bpermute, no LDS storage) for
+                // lanes 0..62; lane 63 takes the next wave's lane 0 at the same
+                // m, or in the last wave wave 0's lane 0 at m + 1, from a few
+                // LDS slots each wave's lane 0 fills ([NW][E + 1]; slot E is
+                // read only for position L, which is never a valid output).
+                // For valid outputs q + 1 <= M/2 + B = L - M/2 stays inside
+                // the segment.
+                constexpr int NW = T / 64;
+                const int lane = t & 63, wave = t >> 6;
+                float2* edge = la;
+                if (lane == 0) {
 #pragma unroll
-                for (int m = 0; m < E; ++m)
-                    la[lds_pad(t + T * m)] = v[m];
+                    for (int m = 0; m < E; ++m)
+                        edge[wave * (E + 1) + m] = v[m];
+                }
                 next();
                 __syncthreads();
-                // both y_r and y_{r+1} are read back from LDS so v is dead here;
-                // for valid outputs q + 1 <= M/2 + B = L - M/2 stays inside the
-                // segment (the clamp only serves positions whose store is dropped)
+                const int src = ((lane + 1) & 63) << 2;
+                const int ew = wave + 1 < NW ? wave + 1 : 0;
+                const int em = wave + 1 < NW ? 0 : 1;
                 constexpr float kQ2 = 0.61685027506808491368f;   // (pi/4)^2
                 const float* row_q0 = plane + 2 * ((int64_t)z * N + out0 - M / 2);
                 const auto rs = seg_rsrc(row_q0, (M / 2 + nvalid) * 8);
-                // in groups of kIbGroup elements, each fenced off from the
-                // scheduler so the reads of later groups are not hoisted
-                // (which would raise the register peak and spill)
 #pragma unroll
-                for (int g = 0; g < E; g += kIbGroup) {
-#pragma unroll
-                    for (int m = g; m < g + kIbGroup; ++m) {
-                        const int q = t + T * m;
-                        const int qn = q + 1 < L ? q + 1 : L - 1;
-                        const float2 a = la[lds_pad(q)], b = la[lds_pad(qn)];
-                        const float p = fmaf(a.x, a.x, a.y * a.y);
-                        const float dx = a.x - b.x, dy = a.y - b.y;
-                        const float h = kQ2 * fmaf(dx, dx, dy * dy);
-                        const u32x2 ph = {__float_as_uint(p), __float_as_uint(h)};
-                        __builtin_amdgcn_raw_buffer_store_b64(ph, rs, seg_off<8>(q, M / 2), 0,
-                                                              kNonTemporal);
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
+                for (int m = 0; m < E; ++m) {
+                    float bx = __int_as_float(
+                        __builtin_amdgcn_ds_bpermute(src, __float_as_int(v[m].x)));
+                    float by = __int_as_float(
+                        __builtin_amdgcn_ds_bpermute(src, __float_as_int(v[m].y)));
+                    const float2 e = edge[ew * (E + 1) + em + m];   // broadcast read
+                    bx = lane == 63 ? e.x : bx;
+                    by = lane == 63 ? e.y : by;
+                    const float p = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
+                    const float dx = v[m].x - bx, dy = v[m].y - by;
+                    const float h = kQ2 * fmaf(dx, dx, dy * dy);
+                    const u32x2 ph = {__float_as_uint(p), __float_as_uint(h)};
+                    __builtin_amdgcn_raw_buffer_store_b64(ph, rs, seg_off<8>(t + T * m, M / 2), 0,
+                                                          kNonTemporal);
                 }
                 float2* tmp = la;
                 la = lb;

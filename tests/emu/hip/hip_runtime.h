@@ -28,6 +28,8 @@ inline float2 make_float2(float a, float b) { return float2{a, b}; }
 
 inline unsigned __float_as_uint(float f) { unsigned u; std::memcpy(&u, &f, 4); return u; }
 inline float __uint_as_float(unsigned u) { float f; std::memcpy(&f, &u, 4); return f; }
+inline int __float_as_int(float f) { int u; std::memcpy(&u, &f, 4); return u; }
+inline float __int_as_float(int u) { float f; std::memcpy(&f, &u, 4); return f; }
 #define __builtin_amdgcn_sched_barrier(x) ((void)0)
 
 // Raw buffer resources: a byte range [base, base + bytes).  As on the GPU,
@@ -89,6 +91,22 @@ inline void __syncthreads() { emu_barrier->arrive_and_wait(); }
 
 using std::max;
 using std::min;
+
+// Cross-lane permute within a 64-lane wave (lane i reads lane (addr/4) mod 64
+// of its own wave).  Emulated through a workgroup-wide buffer between two
+// barriers, so every thread of the workgroup must reach it (as on the GPU,
+// where the kernels call it in uniform control flow).
+#define __builtin_amdgcn_ds_bpermute emu_ds_bpermute
+inline int emu_perm_buf[1024];
+inline int emu_ds_bpermute(int addr, int data)
+{
+    const unsigned t = threadIdx.x;
+    emu_perm_buf[t] = data;
+    __syncthreads();
+    const int v = emu_perm_buf[(t & ~63u) + ((unsigned)(addr >> 2) & 63u)];
+    __syncthreads();
+    return v;
+}
 inline void sincospi(double x, double* s, double* c) { *s = std::sin(M_PI * x); *c = std::cos(M_PI * x); }
 
 typedef int hipError_t;
