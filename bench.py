@@ -2,9 +2,10 @@
 """Benchmark: f-fdot points/s of the fused FDAS forward correlation on one GPU.
 
 Workload: one 2^21-bin complex64 spectrum (seeded noise + 16 injected
-constant-fdot signals), 85 templates z = -84..84 step 2, 256 taps.  A
-selection pass times segment lengths 2048 and 4096; the faster one is then
-measured: `warmup` untimed steps, `steps` timed back to back.  A step is one
+constant-fdot signals), 85 templates z = -84..84 step 2, 256 taps.  After
+half a second of untimed launches, a selection pass times segment lengths
+2048 and 4096 in two interleaved rounds; the faster one is then measured:
+`warmup` untimed steps, `steps` timed back to back.  A step is one
 fdas_correlate call (segment load, forward FFT, 85 template multiplies,
 inverse FFTs, |.|^2, valid-output stores) with the spectrum and the prepared
 bank resident in HBM.  Prints one JSON line.
@@ -439,6 +440,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--L", default="2048,4096", help="segment lengths to time")
+    ap.add_argument("--preheat", type=float, default=0.5,
+                    help="seconds of untimed forward launches before the selection pass")
     ap.add_argument("--grid", type=int, default=0,
                     help="persistent workgroups (0 = as many as the device holds resident)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -484,16 +487,28 @@ def main() -> int:
     print(f"# workload 2: N={N} K={K} M={M}", file=sys.stderr, flush=True)
 
     # segment-length selection pass (not the measurement), then the timed
-    # steps at the chosen length
+    # steps at the chosen length.  The clock climbs over the first tenths of a
+    # second of sustained load, so the device is kept busy for a while first
+    # and the lengths are timed in two interleaved rounds (best of the two).
     per_L, banks = {}, {}
-    for L in [int(x) for x in args.L.split(",")]:
+    lengths = [int(x) for x in args.L.split(",")]
+    for L in lengths:
         _, banks[L] = fdas.make_bank(w.zmax, w.dz, M, L, device=dev)
-        ms, ms_k, _ = time_forward(fdas, torch, spec, N, banks[L], K, M, L, plane, args.steps,
-                                   args.warmup, args.grid)
-        per_L[L] = {"step": ms, "kernel": ms_k}
-        print(f"# select L={L}: {ms:.4f} ms/step, kernel {ms_k:.4f} ms", file=sys.stderr,
-              flush=True)
-    L = min(per_L, key=lambda k: per_L[k]["kernel"])
+    t_end = time.perf_counter() + args.preheat
+    while time.perf_counter() < t_end:
+        for _ in range(20):
+            fdas.fdas_correlate_ex(spec, N, banks[lengths[0]], K, M, lengths[0], plane, args.grid)
+        torch.cuda.synchronize()
+    for rnd in range(2 if len(lengths) > 1 else 0):
+        for L in lengths:
+            ms, ms_k, _ = time_forward(fdas, torch, spec, N, banks[L], K, M, L, plane, args.steps,
+                                       args.warmup, args.grid)
+            prev = per_L.get(L)
+            if prev is None or ms_k < prev["kernel"]:
+                per_L[L] = {"step": ms, "kernel": ms_k}
+            print(f"# select L={L} (round {rnd}): {ms:.4f} ms/step, kernel {ms_k:.4f} ms",
+                  file=sys.stderr, flush=True)
+    L = min(per_L, key=lambda k: per_L[k]["kernel"]) if per_L else lengths[0]
     ms, ms_k, ms_host = time_forward(fdas, torch, spec, N, banks[L], K, M, L, plane, args.steps,
                                      args.warmup, args.grid)
     print(f"# L={L}: {ms:.4f} ms/step, kernel {ms_k:.4f} ms, host enqueue {ms_host:.4f} ms, "
