@@ -222,42 +222,50 @@ def bench_batched(fdas, torch, steps: int):
 
 
 def bench_fwd_bwd(fdas, torch, steps: int):
-    """2^20 bins, 85 x 128 taps, segment 2048: forward alone vs forward plus
-    the adjoint (gradients w.r.t. the spectrum and the taps, w ~ U(0,1))."""
+    """2^20 bins, 85 x 128 taps: forward alone vs forward plus the adjoint
+    (gradients w.r.t. the spectrum and the taps, w ~ U(0,1)) at segment
+    lengths 512, 1024 and 2048; the length with the smallest forward +
+    adjoint time is reported (at L = 512 a transform is one wavefront, so
+    the adjoint's workgroups need no barriers)."""
     import fdas_synth as syn
     w = syn.workload(4)
-    K, M, L = w.K, w.M, w.L
+    K, M = w.K, w.M
     N = len(w.spectra[0])
     spec = torch.from_numpy(w.spectra[0]).cuda()
-    _, bank = fdas.make_bank(w.zmax, w.dz, M, L)
     wt = torch.from_numpy(syn.loss_weights(4, K, N)).cuda()
     plane = torch.empty((K, N), dtype=torch.float32, device="cuda")
     gs = torch.empty(N, dtype=torch.complex64, device="cuda")
     gt = torch.empty((K, M), dtype=torch.complex64, device="cuda")
-    ws = torch.empty(fdas.fdas_backward_workspace_bytes(N, K, M, L, 0), dtype=torch.uint8,
-                     device="cuda")
+    per_L = {}
+    for L in (512, 1024, 2048):
+        _, bank = fdas.make_bank(w.zmax, w.dz, M, L)
+        ws = torch.empty(fdas.fdas_backward_workspace_bytes(N, K, M, L, 0), dtype=torch.uint8,
+                         device="cuda")
 
-    def fwd():
-        fdas.fdas_correlate_ex(spec, N, bank, K, M, L, plane, 0)
+        def fwd():
+            fdas.fdas_correlate_ex(spec, N, bank, K, M, L, plane, 0)
 
-    def bwd():
-        fdas.fdas_correlate_backward(spec, N, bank, K, M, L, wt, gs, gt, ws)
+        def bwd():
+            fdas.fdas_correlate_backward(spec, N, bank, K, M, L, wt, gs, gt, ws)
 
-    def bwd_spec_only():
-        fdas.fdas_correlate_backward(spec, N, bank, K, M, L, wt, gs, None, ws)
+        def bwd_spec_only():
+            fdas.fdas_correlate_backward(spec, N, bank, K, M, L, wt, gs, None, ws)
 
-    fwd(); bwd(); bwd_spec_only()
-    ms_f = _timed(torch, fwd, steps)
-    ms_b = _timed(torch, bwd, steps)
-    ms_bs = _timed(torch, bwd_spec_only, steps)
+        fwd(); bwd(); bwd_spec_only()
+        per_L[L] = {"forward_ms": _timed(torch, fwd, steps), "backward_ms": _timed(torch, bwd, steps),
+                    "backward_spec_only_ms": _timed(torch, bwd_spec_only, steps)}
+        del bank, ws
+    L = min(per_L, key=lambda k: per_L[k]["forward_ms"] + per_L[k]["backward_ms"])
+    ms_f, ms_b = per_L[L]["forward_ms"], per_L[L]["backward_ms"]
     pts = K * N
     out = {"workload": f"2^20 bins, {K} templates x {M} taps, segment {L}",
-           "points": pts,
+           "points": pts, "segment": L,
            "forward_ms": ms_f, "forward_points_per_s": pts / ms_f * 1e3,
-           "backward_ms": ms_b, "backward_spec_only_ms": ms_bs,
+           "backward_ms": ms_b, "backward_spec_only_ms": per_L[L]["backward_spec_only_ms"],
            "fwd_bwd_points_per_s": pts / (ms_f + ms_b) * 1e3,
-           "fwd_bwd_over_fwd_time": (ms_f + ms_b) / ms_f}
-    del spec, wt, plane, ws
+           "fwd_bwd_over_fwd_time": (ms_f + ms_b) / ms_f,
+           "per_segment_ms": {str(k): v for k, v in per_L.items()}}
+    del spec, wt, plane
     torch.cuda.empty_cache()
     return out
 

@@ -177,8 +177,8 @@ def workload(number: int, L: int | None = None, nspec: int | None = None,
     if number == 4:
         spec, sigs = _spectrum(rng, 1 << 20, lambda g, n: [(amp, g.uniform(0, 2 * np.pi),
                                                             524288.4, 20.0)])
-        return Workload(4, [spec], 84.0, 2.0, 128, L or 2048, [sigs],
-                        "2^20 bins, 85 templates x 128 taps, segment 2048")
+        return Workload(4, [spec], 84.0, 2.0, 128, L or 512, [sigs],
+                        "2^20 bins, 85 templates x 128 taps, segment 512")
     raise ValueError(f"unknown workload {number}")
 
 

@@ -318,8 +318,7 @@ int fdas_autotune_batched(const fdas_cf32 *taps_dev, int K, int M, const fdas_cf
 /* ---- real-to-complex front end -------------------------------------------- */
 
 /* Bytes of device workspace fdas_r2c needs for n samples (0 if n is not
- * supported): n/2 complex work values plus two twiddle tables of about
- * 2 sqrt(n) entries. */
+ * supported): n/2 complex work values. */
 size_t fdas_r2c_workspace_bytes(int64_t n);
 
 /*

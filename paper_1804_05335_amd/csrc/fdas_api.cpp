@@ -572,7 +572,7 @@ size_t fdas_r2c_workspace_bytes(int64_t n)
     const int l = r2c_log2n(n);
     if (l < 0)
         return 0;
-    return ((size_t)(n / 2) + fdas::r2c_table_elems(l)) * sizeof(fdas_cf32);
+    return (size_t)(n / 2) * sizeof(fdas_cf32);
 }
 
 int fdas_r2c(const float* x_dev, int64_t n, float scale, fdas_cf32* spec_dev, void* ws_dev,

@@ -45,10 +45,8 @@ hipError_t launch_backward(const float2* spec, int64_t N, const float2* bank, in
 
 // Real-to-complex front end (fdas_r2c.hip).  r2c_plan: radix bits per
 // global pass for N = 2^log2N complex points (pass count, or -1 if
-// unsupported); r2c_table_elems: twiddle-table entries for n = 2^log2n.
-// launch_r2c: ws holds N work values followed by the tables.
+// unsupported).  launch_r2c: ws holds N work values.
 int r2c_plan(int log2N, int bits[4]);
-size_t r2c_table_elems(int log2n);
 hipError_t launch_r2c(const float* x, int log2n, float scale, float2* spec, float2* ws,
                       hipStream_t s);
 

@@ -161,8 +161,10 @@ def test_emulated_interbin_vs_oracle(emu, L, M, N, grid):
 
 @pytest.mark.parametrize("log2n", [13, 14, 15, 16, 17, 18])
 def test_emulated_r2c_vs_oracle(emu, log2n):
-    # plans: 2^12 complex points -> radix bits (6, 6); ... 2^17 -> (6, 6, 5),
-    # so every radix 32..256 and both pass kinds run
+    # plans: 2^12 complex points -> radix bits (6, 6) with the separate split
+    # kernel; 2^13 .. 2^17 -> (7, 6), (7, 7), (8, 7), (8, 8), (6, 6, 5) with
+    # the split inside the last pass, so every radix 32..256 runs as a first,
+    # a middle and a fused last pass
     from oracle import r2c
     n = 1 << log2n
     x = syn.time_series(log2n, n, [(0.3, 0.2, n / 7 + 0.4, 11.0)])

@@ -110,15 +110,20 @@ def test_finite_differences_on_workload4_slice(fd):
         assert abs(np.real(np.vdot(gT, dT)) - fdT) < 1e-5 * abs(fdT) + 1e-5 * np.sum(np.abs(gT) * np.abs(dT))
 
 
-def test_workload4_full(fd):
-    # 2^20 bins, 85 templates x 128 taps, segment 2048, w ~ U(0,1)
+@pytest.fixture(scope="module")
+def workload4_ref(fd):
     w4 = syn.workload(4)
-    A = w4.spectra[0]
-    K = w4.K
     taps = fd.fdas_make_templates_host(w4.zmax, w4.dz, w4.M)
-    w = syn.loss_weights(4, K, len(A))
-    gA, gT = _grads(fd, A, taps, w, w4.L)
-    rA, rT = native.grads(A, taps, w)
+    w = syn.loss_weights(4, w4.K, len(w4.spectra[0]))
+    return w4, taps, w, native.grads(w4.spectra[0], taps, w)
+
+
+@pytest.mark.parametrize("L", [512, 1024, 2048])
+def test_workload4_full(fd, workload4_ref, L):
+    # 2^20 bins, 85 templates x 128 taps, w ~ U(0,1), at each segment length
+    # the forward + adjoint benchmark times
+    w4, taps, w, (rA, rT) = workload4_ref
+    gA, gT = _grads(fd, w4.spectra[0], taps, w, L)
     assert _rel(gA, rA) < TOL
     assert _rel(gT, rT) < TOL
 
