@@ -260,8 +260,10 @@ int fdas_correlate_batched_ex(const fdas_cf32 *specs_dev, const int64_t *offsets
 
 /* Bytes of device workspace for fdas_correlate_backward(_ex) with the same
  * (N, K, M, L, zchunk; 0 = default), a multiple of 256; 0 for an invalid
- * geometry.  Holds the per-window partial gradients:
- * ceil(K/zchunk) * ceil(N/B) * L + ceil(N/B) * K * M complex values. */
+ * geometry.  Holds the per-window partial gradients,
+ * ceil(K/zchunk) * ceil(N/B) * L + ceil(N/B) * K * M complex values, and
+ * up to 2048 / ceil(K M / 64) chunk sums of the taps gradient (K * M FP64
+ * complex values each). */
 size_t fdas_backward_workspace_bytes(int64_t N, int K, int M, int L, int zchunk);
 
 /*

@@ -474,15 +474,33 @@ int backward_zchunk(int64_t nwin, int K, int zchunk)
     return (int)((K + chunks - 1) / chunks);
 }
 
-void backward_layout(int64_t N, int K, int M, int L, int zchunk, size_t* offT, size_t* total)
+// Window chunks of the taps-gradient reduction: enough (64 x 16)-lane blocks
+// to fill the device (~2048 over the K M / 64 column groups), each chunk at
+// least 64 windows long.
+int backward_tsplit(int64_t nwin, int K, int M)
+{
+    const int64_t groups = ((int64_t)K * M + 63) / 64;
+    int64_t split = (2048 + groups - 1) / groups;
+    const int64_t most = nwin / 64;
+    if (split > most) split = most;
+    if (split < 1) split = 1;
+    return (int)split;
+}
+
+// Workspace: partA [nzc][nwin][L] complex, partT [nwin][K][M] complex, tpart
+// [tsplit][K][M] FP64 complex, each 256-byte aligned.
+void backward_layout(int64_t N, int K, int M, int L, int zchunk, size_t* offT, size_t* offP,
+                     size_t* total)
 {
     const int64_t nwin = (N + (L - M) - 1) / (L - M);
     const int zc = backward_zchunk(nwin, K, zchunk);
     const int64_t nzc = (K + zc - 1) / zc;
     const size_t a = (size_t)nzc * (size_t)nwin * (size_t)L * sizeof(fdas_cf32);
     const size_t t = (size_t)nwin * (size_t)K * (size_t)M * sizeof(fdas_cf32);
+    const size_t p = (size_t)backward_tsplit(nwin, K, M) * (size_t)K * (size_t)M * 2 * sizeof(double);
     *offT = (a + 255) & ~(size_t)255;
-    *total = ((*offT + t) + 255) & ~(size_t)255;
+    *offP = ((*offT + t) + 255) & ~(size_t)255;
+    *total = ((*offP + p) + 255) & ~(size_t)255;
 }
 
 }  // namespace
@@ -491,8 +509,8 @@ size_t fdas_backward_workspace_bytes(int64_t N, int K, int M, int L, int zchunk)
 {
     if (N < 0 || N > kMaxN || check_geometry(K, M, L) != FDAS_OK || zchunk < 0 || zchunk > K)
         return 0;
-    size_t offT = 0, total = 0;
-    backward_layout(N, K, M, L, zchunk, &offT, &total);
+    size_t offT = 0, offP = 0, total = 0;
+    backward_layout(N, K, M, L, zchunk, &offT, &offP, &total);
     return total < 256 ? 256 : total;
 }
 
@@ -523,14 +541,15 @@ int fdas_correlate_backward_ex(const fdas_cf32* spec_dev, int64_t N, const fdas_
                     need);
     const int64_t nwin = (N + (L - M) - 1) / (L - M);
     const int zc = backward_zchunk(nwin, K, zchunk);
-    size_t offT = 0, total = 0;
-    backward_layout(N, K, M, L, zchunk, &offT, &total);
+    size_t offT = 0, offP = 0, total = 0;
+    backward_layout(N, K, M, L, zchunk, &offT, &offP, &total);
     auto* base = static_cast<unsigned char*>(ws_dev);
     hipError_t e = fdas::launch_backward(
         reinterpret_cast<const float2*>(spec_dev), N, reinterpret_cast<const float2*>(bank_dev),
         K, M, L, dLdP_dev, reinterpret_cast<float2*>(grad_spec_dev),
         reinterpret_cast<float2*>(grad_taps_dev), zc, reinterpret_cast<float2*>(base),
-        reinterpret_cast<float2*>(base + offT), stream);
+        reinterpret_cast<float2*>(base + offT), backward_tsplit(nwin, K, M),
+        reinterpret_cast<double2*>(base + offP), stream);
     if (e != hipSuccess)
         return hip_fail(e, "backward launch");
     return ok();

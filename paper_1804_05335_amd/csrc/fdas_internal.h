@@ -38,10 +38,13 @@ hipError_t launch_batched(const float2* specs, const int64_t* offsets, int nspec
                           int64_t* segpre, int grid, hipStream_t s);
 
 // Adjoint: window kernel into partA [nzc][nwin][L] / partT [nwin][K][M], then
-// the FP64 reductions into grad_spec [N] / grad_taps [K][M] (either may be null).
+// the FP64 reductions into grad_spec [N] / grad_taps [K][M] (either may be
+// null); the taps reduction sums tsplit window chunks into tpart
+// [tsplit][K][M] (FP64) first.
 hipError_t launch_backward(const float2* spec, int64_t N, const float2* bank, int K, int M,
                           int L, const float* dLdP, float2* grad_spec, float2* grad_taps,
-                          int zchunk, float2* partA, float2* partT, hipStream_t s);
+                          int zchunk, float2* partA, float2* partT, int tsplit, double2* tpart,
+                          hipStream_t s);
 
 // Real-to-complex front end (fdas_r2c.hip).  r2c_plan: radix bits per
 // global pass for N = 2^log2N complex points (pass count, or -1 if

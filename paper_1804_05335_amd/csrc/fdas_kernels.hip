@@ -563,21 +563,27 @@ __global__ void reduce_grad_spec_kernel(const float2* __restrict__ partA, int64_
     grad[k] = make_float2((float)sr, (float)si);
 }
 
-// grad_T[z][j] = (1/L) sum_s partT[s][z][j] in FP64.  A block covers
-// kTapsCols consecutive (z, j) entries with kTapsRows lanes each; lane row q
-// sums windows s = q, q + kTapsRows, ... and the rows are then added in
-// order q = 0, 1, ..., so the result is deterministic.
+// grad_T[z][j] = (1/L) sum_s partT[s][z][j] in FP64, in two fixed-order
+// stages.  Stage 1: block (x, y) covers kTapsCols consecutive (z, j) entries
+// and the windows s of chunk y; lane row q sums s = s0 + q, s0 + q +
+// kTapsRows, ..., the rows are added in order q = 0, 1, ..., and the FP64
+// sum goes to tpart[y][(z, j)].  Stage 2 adds the chunks in order y = 0,
+// 1, ... and scales.  The chunking depends only on the geometry, so the
+// result is deterministic.
 constexpr int kTapsCols = 64, kTapsRows = 16;
 
 __global__ __launch_bounds__(kTapsCols * kTapsRows) void reduce_grad_taps_kernel(
-    const float2* __restrict__ partT, int64_t nwin, int KM, int L, float2* __restrict__ grad)
+    const float2* __restrict__ partT, int64_t nwin, int64_t chunk, int KM,
+    double2* __restrict__ tpart)
 {
     __shared__ double part[kTapsRows][kTapsCols][2];
     const int c = threadIdx.x % kTapsCols, q = threadIdx.x / kTapsCols;
     const int i = blockIdx.x * kTapsCols + c;
+    const int64_t s0 = (int64_t)blockIdx.y * chunk;
+    const int64_t s1 = min(nwin, s0 + chunk);
     double sr = 0.0, si = 0.0;
     if (i < KM)
-        for (int64_t s = q; s < nwin; s += kTapsRows) {
+        for (int64_t s = s0 + q; s < s1; s += kTapsRows) {
             const float2 v = partT[s * KM + i];
             sr += v.x;
             si += v.y;
@@ -591,9 +597,24 @@ __global__ __launch_bounds__(kTapsCols * kTapsRows) void reduce_grad_taps_kernel
             tr += part[r][c][0];
             ti += part[r][c][1];
         }
-        const double inv = 1.0 / (double)L;
-        grad[i] = make_float2((float)(tr * inv), (float)(ti * inv));
+        tpart[(int64_t)blockIdx.y * KM + i] = make_double2(tr, ti);
     }
+}
+
+__global__ void reduce_grad_taps_final_kernel(const double2* __restrict__ tpart, int nsplit,
+                                              int KM, int L, float2* __restrict__ grad)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= KM)
+        return;
+    double tr = 0.0, ti = 0.0;
+    for (int y = 0; y < nsplit; ++y) {
+        const double2 v = tpart[(int64_t)y * KM + i];
+        tr += v.x;
+        ti += v.y;
+    }
+    const double inv = 1.0 / (double)L;
+    grad[i] = make_float2((float)(tr * inv), (float)(ti * inv));
 }
 
 // ---- launchers -------------------------------------------------------------------
@@ -737,7 +758,8 @@ static hipError_t launch_backward_L(const float2* spec, int64_t N, const float2*
 
 hipError_t launch_backward(const float2* spec, int64_t N, const float2* bank, int K, int M,
                           int L, const float* dLdP, float2* grad_spec, float2* grad_taps,
-                          int zchunk, float2* partA, float2* partT, hipStream_t s)
+                          int zchunk, float2* partA, float2* partT, int tsplit, double2* tpart,
+                          hipStream_t s)
 {
     const int64_t nwin = (N + (L - M) - 1) / (L - M);
     const int want_A = grad_spec != nullptr, want_T = grad_taps != nullptr;
@@ -765,8 +787,14 @@ hipError_t launch_backward(const float2* spec, int64_t N, const float2* bank, in
     }
     if (want_T) {
         const int KM = K * M;
-        hipLaunchKernelGGL(reduce_grad_taps_kernel, dim3((KM + kTapsCols - 1) / kTapsCols),
-                           dim3(kTapsCols * kTapsRows), 0, s, partT, nwin, KM, L, grad_taps);
+        const int64_t chunk = nwin > 0 ? (nwin + tsplit - 1) / tsplit : 1;
+        hipLaunchKernelGGL(reduce_grad_taps_kernel,
+                           dim3((KM + kTapsCols - 1) / kTapsCols, (unsigned)tsplit),
+                           dim3(kTapsCols * kTapsRows), 0, s, partT, nwin, chunk, KM, tpart);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(reduce_grad_taps_final_kernel, dim3((KM + bs - 1) / bs), dim3(bs), 0,
+                           s, tpart, tsplit, KM, L, grad_taps);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }

@@ -25,6 +25,8 @@
 
 struct float2 { float x, y; };
 inline float2 make_float2(float a, float b) { return float2{a, b}; }
+struct double2 { double x, y; };
+inline double2 make_double2(double a, double b) { return double2{a, b}; }
 
 inline unsigned __float_as_uint(float f) { unsigned u; std::memcpy(&u, &f, 4); return u; }
 inline float __uint_as_float(unsigned u) { float f; std::memcpy(&f, &u, 4); return f; }
