@@ -1,0 +1,54 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU guard, the algorithmic
+work model the roofline uses, and the rule that HBM traffic is read from a
+counter summary only when it was taken from the current kernel sources."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_forward_work_model_at_the_headline_size():
+    # 2^21 bins, 85 templates x 256 taps, L = 2048: B = 1792, S = ceil(N / B)
+    N, K, M, L = 1 << 21, 85, 256, 2048
+    S = -(-N // (L - M))
+    assert S == 1171
+    nbytes, flops = bench.forward_work(N, K, M, L)
+    # spectrum read once, plane written once, bank read once
+    assert nbytes == 8 * N + 4 * K * N + 8 * K * L
+    fft = 4.25 * L * 11
+    assert flops == S * fft + S * K * (6 * L + fft) + 3 * K * N
+
+
+def _summary(path, khash, fetch, write):
+    with open(path, "w") as f:
+        f.write("# summary\n\n| counter | value |\n|---|---|\n| FETCH_SIZE | 1 KiB |\n\n")
+        f.write(f"kernel_sources_hash: {khash}\n")
+        f.write(f"fetch_bytes_per_launch: {fetch}\nwrite_bytes_per_launch: {write}\n")
+
+
+def test_traffic_only_from_summaries_of_the_current_sources(tmp_path, monkeypatch):
+    cur = bench.kernel_sources_hash()
+    os.makedirs(tmp_path / "profiles")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_sources_hash", lambda: cur)
+    _summary(tmp_path / "profiles" / "now.md", cur, 100, 23)
+    _summary(tmp_path / "profiles" / "old.md", "0" * 16, 100, 23)
+    assert bench.read_traffic("now.md") == 123.0
+    assert bench.read_traffic("old.md") is None
+    assert bench.read_traffic("missing.md") is None
+
+
+def test_kernel_sources_hash_is_stable_and_short():
+    a, b = bench.kernel_sources_hash(), bench.kernel_sources_hash()
+    assert a == b and len(a) == 16 and int(a, 16) >= 0
