@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0                      # MI355X HBM3E, GB/s
-# FP32 vector peak without packed-FP32 instructions (disabled in this build):
+# FP32 vector peak without packed-FP32 instructions (the library is compiled without them):
 # 256 CUs x 64 FP32 lanes x 2 flop (FMA) x 2.4 GHz
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 
@@ -463,7 +463,7 @@ def main() -> int:
                     help="first run one plain device copy of BYTES (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
+        print(f"bench.py: runs on one GPU only (got --gpus {args.gpus}); "
               "the forward path shards by spectrum or segment range with no exchange, "
               "but no multi-GPU run is implemented.", file=sys.stderr)
         return 2

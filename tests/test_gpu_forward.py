@@ -1,6 +1,6 @@
 """GPU parity of the fused forward correlation against the FP64 oracle.
 
-Bar (spec tolerance): max |P_gpu - P_oracle| / max P_oracle <= 1e-5,
+Bar: max |P_gpu - P_oracle| / max P_oracle <= 1e-5 (FP32 kernels, FP64 oracle),
 with the oracle using its own closed-form templates and the GPU the
 library's.  Full planes at the small workload (2^16 bins, 21 x 64 taps) for
 every segment length, ragged and degenerate sizes with arbitrary taps, and
