@@ -81,6 +81,21 @@ def test_grads_partial_requests_and_zchunks(fd):
     assert np.array_equal(again[0], ref[0]) and np.array_equal(again[1], ref[1])
 
 
+def test_largest_template_count(fd):
+    # K = 4096, the largest bank the ABI accepts: one template per workgroup
+    # chunk would be 4096 chunks, so the default chunking and both reductions
+    # run at their extreme
+    L, M, K = 256, 16, 4096
+    N = 3 * (L - M) + 5
+    A = syn.random_spectrum(21, N)
+    taps = syn.random_taps(22, K, M)
+    w = np.random.default_rng(23).random((K, N), dtype=np.float32)
+    gA, gT = _grads(fd, A, taps, w, L)
+    rA, rT = native.grads(A, taps, w)
+    assert _rel(gA, rA) < TOL
+    assert _rel(gT, rT) < TOL
+
+
 def test_empty_spectrum_gives_zero_taps_gradient(fd):
     taps = syn.random_taps(4, 3, 16)
     gA, gT = _grads(fd, np.zeros(0, np.complex64), taps, np.zeros((3, 0), np.float32), 256)

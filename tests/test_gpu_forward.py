@@ -95,6 +95,19 @@ def test_ragged_and_degenerate_sizes_random_taps(fd, L, case):
     assert _rel(P, ref) < TOL
 
 
+@pytest.mark.parametrize("L", [256, 2048])
+def test_largest_template_count(fd, L):
+    # K = 4096, the largest bank the ABI accepts, on a ragged spectrum
+    K, M = 4096, 16
+    N = 3 * (L - M) + 5
+    taps = syn.random_taps(K + L, K, M)
+    bank = fd.prepare_bank(_dev(taps), L)
+    A = syn.random_spectrum(K + 1, N)
+    P = _plane(fd, A, bank, K, M, L)
+    assert P.shape == (K, N)
+    assert _rel(P, native.power(A, taps)) < TOL
+
+
 def test_empty_spectrum_is_a_noop(fd):
     taps = syn.random_taps(0, 2, 16)
     bank = fd.prepare_bank(_dev(taps), 256)
