@@ -10,6 +10,9 @@ Modules:
   templates  closed-form templates R(q, z) and the bank T[K][M]  (Sec. 2, eq. 23)
   direct     numpy FP64 correlation, power plane, loss gradients
   native     the same correlation and gradients in plain C + OpenMP (FP64)
+  r2c        the real-to-complex transform of a time series (literal DFT)
+  harmonic   harmonic sums of the power plane and peak candidates (FP32 sums
+             in a fixed order, so threshold decisions match bit for bit)
 
 Pins (tests marked "not gpu"): quadrature of the defining integral, the
 z = 0 template as a Kronecker delta, conjugate symmetry of +/-z templates,
