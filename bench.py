@@ -442,6 +442,61 @@ def bench_r2c(fdas, torch, steps: int):
     return out
 
 
+def bench_harmonic(fdas, torch, steps: int):
+    """Harmonic sums of the headline plane (85 x 2^21, computed here by the
+    correlation at L = 2048): folds H = 2, 4, ..., 32, each built on the
+    previous one, then the peak candidates of the 32-fold sum above a
+    threshold at ~3e-5 of its points.  Algorithmic bytes of a fold: the
+    H/2 new plane terms, the previous fold and the output, 4 B each per
+    fold point (the gathers of harmonic h use one float in h, so the
+    fetched bytes are higher; see the counter summaries)."""
+    import fdas_synth as syn
+    w = syn.workload(2)
+    N, K, M = len(w.spectra[0]), w.K, w.M
+    spec = torch.from_numpy(w.spectra[0]).cuda()
+    _, bank = fdas.make_bank(w.zmax, w.dz, M, 2048)
+    plane = torch.empty((K, N), dtype=torch.float32, device="cuda")
+    fdas.fdas_correlate_ex(spec, N, bank, K, M, 2048, plane, 0)
+    folds, outs = [2, 4, 8, 16, 32], []
+    for H in folds:
+        KH, NH = fdas.fdas_harmonic_shape(N, K, H)
+        outs.append(torch.empty((KH, NH), dtype=torch.float32, device="cuda"))
+
+    def all_folds():
+        for i, H in enumerate(folds):
+            fdas.fdas_harmonic_sum(plane, N, K, H, outs[i - 1] if i else None, outs[i])
+
+    all_folds()
+    out = {"workload": f"plane {K} x 2^21 (the headline correlation), folds 2..32", "folds": {}}
+    total_ms, total_bytes = 0.0, 0
+    for i, H in enumerate(folds):
+        def one(i=i, H=H):
+            fdas.fdas_harmonic_sum(plane, N, K, H, outs[i - 1] if i else None, outs[i])
+        ms = _timed(torch, one, max(steps, 10))
+        pts = outs[i].numel()
+        alg = pts * 4 * ((H - H // 2 if i else H) + (1 if i else 0) + 1)
+        out["folds"][str(H)] = {"ms": ms, "points": pts, "algorithmic_GB_per_s": alg / ms / 1e6}
+        total_ms += ms
+        total_bytes += alg
+    out["all_folds_ms"] = _timed(torch, all_folds, max(steps, 10))
+    out["all_folds_algorithmic_GB_per_s"] = total_bytes / out["all_folds_ms"] / 1e6
+    S = outs[-1]
+    thr = float(torch.quantile(S.reshape(-1)[: 1 << 24].float(), 1 - 3e-5).item())
+    cap = 1 << 16
+    cbuf = torch.empty(cap * 16, dtype=torch.uint8, device="cuda")
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def cands():
+        fdas.fdas_find_candidates(S, N, K, 32, thr, cbuf, cap, count)
+
+    cands()
+    out["candidates_32fold"] = {"threshold": thr, "count": int(count.item()),
+                                "ms": _timed(torch, cands, max(steps, 10))}
+    del plane, outs, spec, bank, cbuf
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -456,7 +511,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and forward+backward comparisons")
-    ap.add_argument("--extras", default="batched,fwd_bwd,large_zmax,interbin,sym,r2c",
+    ap.add_argument("--extras", default="batched,fwd_bwd,large_zmax,interbin,sym,r2c,harmonic",
                     help="comma-separated extra comparisons to run")
     ap.add_argument("--extra-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -564,7 +619,8 @@ def main() -> int:
     del plane
     torch.cuda.empty_cache()
     extras = {"batched": bench_batched, "fwd_bwd": bench_fwd_bwd, "large_zmax": bench_workload5,
-              "interbin": bench_interbin, "sym": bench_sym, "r2c": bench_r2c}
+              "interbin": bench_interbin, "sym": bench_sym, "r2c": bench_r2c,
+              "harmonic": bench_harmonic}
     for name in ([] if args.no_extras else [x for x in args.extras.split(",") if x]):
         out[name] = extras[name](fdas, torch, args.extra_steps)
         print(f"# {name}: {json.dumps(out[name])}", file=sys.stderr, flush=True)

@@ -27,7 +27,12 @@ Workloads (seed = workload number, numpy PCG64):
   3  256 ragged spectra, N_b log-uniform in [2^18, 2^21], one signal each
      (r~U[0.05,0.95]*N_b, z~U[-60,60]); 85 templates x 256 taps.
   4  one 2^20-bin spectrum, one signal r=524288.4, z=20; 85 templates x 128
-     taps, segment 2048; loss weights w~U(0,1) of shape [K][N].
+     taps, segment 512; loss weights w~U(0,1) of shape [K][N].
+
+Also: random spectra and taps for edge cases, real time series (optionally
+with a pulsed signal: harmonics h r0, h z0 of one constant-fdot signal) for
+the real-to-complex front end, and unit-mean exponential power planes for
+the steps that consume the plane.
   5  64 ragged spectra, N_b log-uniform in [2^21, 2^22], 4 signals each with
      z~U[-190,190]; 201 templates x 512 taps, segment 8192.
 
@@ -217,3 +222,22 @@ def random_taps(seed: int, K: int, M: int) -> np.ndarray:
     """Arbitrary complex taps (not templates) for bank-independent tests."""
     rng = np.random.default_rng(seed)
     return (noise(rng, K * M) / math.sqrt(M)).reshape(K, M).astype(np.complex64)
+
+
+def random_plane(seed: int, K: int, n: int) -> np.ndarray:
+    """A [K][n] float32 power plane of unit-mean exponential values (the
+    power statistics of normalised complex Gaussian noise), for tests and
+    timings of the steps that consume the plane."""
+    rng = np.random.default_rng([seed, K, n])
+    return rng.exponential(size=(K, n)).astype(np.float32)
+
+
+def pulsed_series(seed: int, n: int, r0: float, z0: float, harmonics: int, amp: float,
+                  sigma: float = 1.0) -> np.ndarray:
+    """Noise plus a pulsed constant-fdot signal: a sum of real sinusoids at
+    the harmonics h = 1..harmonics of (r0, z0), i.e. at (h r0, h z0), each
+    of amplitude amp and a seeded phase (a pulse train narrow enough that
+    its first harmonics carry equal power)."""
+    rng = np.random.default_rng([seed, 7])
+    sig = [(amp, rng.uniform(0, 2 * np.pi), h * r0, h * z0) for h in range(1, harmonics + 1)]
+    return time_series(seed, n, sig, sigma)

@@ -342,6 +342,61 @@ size_t fdas_r2c_workspace_bytes(int64_t n);
 int fdas_r2c(const float *x_dev, int64_t n, float scale, fdas_cf32 *spec_dev, void *ws_dev,
              size_t ws_bytes, hipStream_t stream);
 
+/* ---- harmonic summing and peak candidates ---------------------------------- */
+
+/*
+ * Harmonic sums of the f-fdot plane (Sec. 3: the powers of a pulsed
+ * signal's harmonics are added to that of its fundamental before the search
+ * for peaks; the paper names the step without a formula).  A constant-fdot
+ * signal at (r, z) has its h-th harmonic at (h r, h z), so on a plane
+ * P[K][N] with rows z_k = (k - c) dz, c = (K - 1)/2 (fdas_correlate's
+ * layout, K odd), the H-fold sum at the fundamental (k, r) is
+ *     S_H[k][r] = sum_{h=1}^{H} P[c + h (k - c)][h r],
+ * for the fundamentals whose harmonics all lie on the plane: r in
+ * [0, N_H), N_H = ceil(N/H), and |k - c| <= floor(c/H), i.e. K_H =
+ * 2 floor(c/H) + 1 rows; S_H is stored [K_H][N_H] row-major, its row i
+ * being plane row c - floor(c/H) + i.  The sum is formed in FP32 in the
+ * order h = 1..H.
+ */
+
+/* K_H and N_H of the H-fold sum (K odd in [1, 4096], H a power of two in
+ * [1, 64], N in [0, 2^32]); FDAS_INVALID_ARG otherwise. */
+int fdas_harmonic_shape(int64_t N, int K, int H, int *KH, int64_t *NH);
+
+/*
+ * S_H of plane_dev [K][N] into sums_dev [K_H][N_H] (fully overwritten).
+ * prev_dev: NULL, or the H/2-fold sum of the same plane (H >= 2); then only
+ * harmonics H/2 + 1 .. H are read from the plane and added to it, and the
+ * result is bitwise the same as from scratch.  Buffers are device float
+ * arrays (4-byte aligned); sums_dev must not overlap plane_dev or prev_dev.
+ * Asynchronous on `stream`; no allocation.
+ */
+int fdas_harmonic_sum(const float *plane_dev, int64_t N, int K, int H, const float *prev_dev,
+                      float *sums_dev, hipStream_t stream);
+
+/* One candidate: the fundamental's frequency bin, its template row in the
+ * plane (z = (row - (K-1)/2) dz) and its H-fold summed power. */
+typedef struct {
+    int64_t r;
+    int32_t row;
+    float power;
+} fdas_candidate;
+
+/*
+ * Candidates of one fold (Sec. 2: the power is compared with a precomputed
+ * threshold; Sec. 3: the search is for peaks): the points of S_H (sums_dev,
+ * [K_H][N_H] as fdas_harmonic_sum writes it for this N, K, H) whose value
+ * exceeds `threshold` and is >= each of its up to 8 neighbours inside the
+ * fold.  *count_dev (device unsigned) receives the number of such points;
+ * the first min(count, capacity) of them are written to out_dev (device,
+ * 8-byte aligned) in no particular order.  The call zeroes *count_dev
+ * itself (with a kernel, so it can be captured in a graph).  Asynchronous
+ * on `stream`; no allocation.
+ */
+int fdas_find_candidates(const float *sums_dev, int64_t N, int K, int H, float threshold,
+                         fdas_candidate *out_dev, int capacity, unsigned *count_dev,
+                         hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

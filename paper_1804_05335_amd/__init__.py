@@ -19,7 +19,8 @@ from ._lib import (FdasError, fdas_backward_workspace_bytes, fdas_bank_elems,  #
                    fdas_r2c, fdas_r2c_workspace_bytes, fdas_template_response, fdas_version,
                    fdas_bank_sym_elems, fdas_correlate_sym, fdas_correlate_sym_ex,
                    fdas_prepare_bank_sym, fdas_make_templates_half, fdas_correlate_fourier2,
-                   fdas_correlate_fourier2_ex, lib)
+                   fdas_correlate_fourier2_ex, fdas_harmonic_shape, fdas_harmonic_sum,
+                   fdas_find_candidates, lib)
 
 
 def make_bank(zmax: float, dz: float, M: int, L: int, device="cuda"):
@@ -150,3 +151,36 @@ def correlate_fourier2(spec, bank, bank_half, K: int, M: int, L: int, plane2=Non
         plane2 = torch.empty((K, 2 * N), dtype=torch.float32, device=spec.device)
     fdas_correlate_fourier2_ex(spec, N, bank, bank_half, K, M, L, plane2, grid)
     return plane2
+
+
+def harmonic_sums(plane, max_fold: int):
+    """[S_1 = plane, S_2, S_4, ..., S_max_fold] of a [K][N] float32 plane
+    (Sec. 3 harmonic summing), each fold built on the previous one."""
+    import torch
+    K, N = plane.shape
+    folds = [plane]
+    H = 2
+    while H <= max_fold:
+        KH, NH = fdas_harmonic_shape(N, K, H)
+        out = torch.empty((KH, NH), dtype=torch.float32, device=plane.device)
+        fdas_harmonic_sum(plane, N, K, H, folds[-1] if H > 2 else None, out)
+        folds.append(out)
+        H *= 2
+    return folds
+
+
+def candidates(sums, N: int, K: int, H: int, threshold: float, capacity: int = 1 << 16):
+    """Peaks of one fold above `threshold` (Sec. 2/3): (r int64, row int32,
+    power float32) host arrays sorted by (row, r), and the total count
+    (which may exceed `capacity`; then only `capacity` are returned)."""
+    import numpy as np
+    import torch
+    out = torch.empty(max(capacity, 1) * 16, dtype=torch.uint8, device=sums.device)
+    count = torch.zeros(1, dtype=torch.int32, device=sums.device)
+    fdas_find_candidates(sums, N, K, H, threshold, out, capacity, count)
+    n = int(count.item())
+    rec = np.frombuffer(out.cpu().numpy().tobytes(), dtype=np.dtype(
+        [("r", "<i8"), ("row", "<i4"), ("power", "<f4")]))[:min(n, capacity)]
+    order = np.lexsort((rec["r"], rec["row"]))
+    rec = rec[order]
+    return rec["r"].copy(), rec["row"].copy(), rec["power"].copy(), n

@@ -59,7 +59,13 @@ SIGNATURES = [
     ("fdas_correlate_fourier2_ex", _I, [_P, _I64, _P, _P, _I, _I, _I, _P, _I, _P]),
     ("fdas_r2c_workspace_bytes", _SZ, [_I64]),
     ("fdas_r2c", _I, [_P, _I64, ctypes.c_float, _P, _P, _SZ, _P]),
+    ("fdas_harmonic_shape", _I, [_I64, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I64)]),
+    ("fdas_harmonic_sum", _I, [_P, _I64, _I, _I, _P, _P, _P]),
+    ("fdas_find_candidates", _I, [_P, _I64, _I, _I, ctypes.c_float, _P, _I, _P, _P]),
 ]
+
+# fdas_candidate: {int64 r; int32 row; float power} (16 bytes)
+CANDIDATE_BYTES = 16
 
 
 class FdasError(RuntimeError):
@@ -346,3 +352,37 @@ def fdas_correlate_fourier2_ex(spec, N: int, bank, bank_half, K: int, M: int, L:
     _check(lib().fdas_correlate_fourier2_ex(_ptr(spec), N, _ptr(bank), _ptr(bank_half), K, M, L,
                                             _ptr(plane2), grid, _stream(stream, spec)),
            "fdas_correlate_fourier2")
+
+
+def fdas_harmonic_shape(N: int, K: int, H: int):
+    """(K_H, N_H) of the H-fold harmonic sum of a [K][N] plane."""
+    kh, nh = _I(), _I64()
+    _check(lib().fdas_harmonic_shape(N, K, H, ctypes.byref(kh), ctypes.byref(nh)),
+           "fdas_harmonic_shape")
+    return kh.value, nh.value
+
+
+def fdas_harmonic_sum(plane, N: int, K: int, H: int, prev, sums, stream=None) -> None:
+    import torch
+    KH, NH = fdas_harmonic_shape(N, K, H)
+    _require(plane, torch.float32, "plane", K * N)
+    if prev is not None:
+        KHp, NHp = fdas_harmonic_shape(N, K, H // 2)
+        _require(prev, torch.float32, "prev", KHp * NHp)
+    _require(sums, torch.float32, "sums", KH * NH)
+    _check(lib().fdas_harmonic_sum(_ptr(plane), N, K, H, _ptr(prev), _ptr(sums),
+                                   _stream(stream, plane)), "fdas_harmonic_sum")
+
+
+def fdas_find_candidates(sums, N: int, K: int, H: int, threshold: float, out, capacity: int,
+                         count, stream=None) -> None:
+    """out: uint8 device tensor of capacity * 16 bytes (fdas_candidate
+    records); count: int32 device tensor of one element."""
+    import torch
+    KH, NH = fdas_harmonic_shape(N, K, H)
+    _require(sums, torch.float32, "sums", KH * NH)
+    _require(out, torch.uint8, "out", capacity * CANDIDATE_BYTES)
+    _require(count, torch.int32, "count", 1)
+    _check(lib().fdas_find_candidates(_ptr(sums), N, K, H, threshold, _ptr(out), capacity,
+                                      _ptr(count), _stream(stream, sums)),
+           "fdas_find_candidates")

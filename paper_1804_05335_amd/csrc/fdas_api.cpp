@@ -623,3 +623,98 @@ int fdas_r2c(const float* x_dev, int64_t n, float scale, fdas_cf32* spec_dev, vo
 }
 
 }  // extern "C"
+
+// ---- harmonic summing and peak candidates ---------------------------------------
+
+namespace {
+
+int check_harmonic(int64_t N, int K, int H)
+{
+    if (N < 0 || N > kMaxN)
+        return fail(FDAS_INVALID_ARG, "N = %lld outside [0, 2^32]", (long long)N);
+    if (K < 1 || K > kMaxK || (K & 1) == 0)
+        return fail(FDAS_INVALID_ARG, "K = %d must be odd in [1, %d]", K, kMaxK);
+    if (!is_pow2(H) || H > 64)
+        return fail(FDAS_INVALID_ARG, "H = %d must be a power of two in [1, 64]", H);
+    return FDAS_OK;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb)
+{
+    const auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+    return a && b && pa < pb + nb && pb < pa + na;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fdas_harmonic_shape(int64_t N, int K, int H, int* KH, int64_t* NH)
+{
+    const int st = check_harmonic(N, K, H);
+    if (st)
+        return st;
+    if (!KH || !NH)
+        return fail(FDAS_INVALID_ARG, "KH and NH must not be NULL");
+    fdas::harmonic_shape(N, K, H, KH, NH);
+    return ok();
+}
+
+int fdas_harmonic_sum(const float* plane_dev, int64_t N, int K, int H, const float* prev_dev,
+                      float* sums_dev, hipStream_t stream)
+{
+    const int st = check_harmonic(N, K, H);
+    if (st)
+        return st;
+    if (prev_dev && H < 2)
+        return fail(FDAS_INVALID_ARG, "a previous fold needs H >= 2");
+    int KH = 0, KHp = 0;
+    int64_t NH = 0, NHp = 0;
+    fdas::harmonic_shape(N, K, H, &KH, &NH);
+    if (NH == 0)
+        return ok();
+    if (!plane_dev || !sums_dev)
+        return fail(FDAS_INVALID_ARG, "plane and sums must not be NULL");
+    if (!aligned(plane_dev, 4) || !aligned(sums_dev, 4) || (prev_dev && !aligned(prev_dev, 4)))
+        return fail(FDAS_INVALID_ARG, "misaligned pointer (4 B)");
+    const size_t out_bytes = (size_t)KH * (size_t)NH * sizeof(float);
+    if (overlaps(sums_dev, out_bytes, plane_dev, (size_t)K * (size_t)N * sizeof(float)))
+        return fail(FDAS_INVALID_ARG, "sums must not overlap the plane");
+    if (prev_dev) {
+        fdas::harmonic_shape(N, K, H / 2, &KHp, &NHp);
+        if (overlaps(sums_dev, out_bytes, prev_dev, (size_t)KHp * (size_t)NHp * sizeof(float)))
+            return fail(FDAS_INVALID_ARG, "sums must not overlap the previous fold");
+    }
+    const hipError_t e =
+        fdas::launch_harmonic_sum(plane_dev, N, K, H, prev_dev, sums_dev, stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "harmonic sum launch");
+    return ok();
+}
+
+int fdas_find_candidates(const float* sums_dev, int64_t N, int K, int H, float threshold,
+                         fdas_candidate* out_dev, int capacity, unsigned* count_dev,
+                         hipStream_t stream)
+{
+    const int st = check_harmonic(N, K, H);
+    if (st)
+        return st;
+    if (capacity < 0)
+        return fail(FDAS_INVALID_ARG, "capacity = %d must be >= 0", capacity);
+    if (!count_dev || !aligned(count_dev, 4))
+        return fail(FDAS_INVALID_ARG, "count must be a 4-byte aligned device pointer");
+    if (capacity > 0 && (!out_dev || !aligned(out_dev, 8)))
+        return fail(FDAS_INVALID_ARG, "out must be an 8-byte aligned device pointer");
+    int KH = 0;
+    int64_t NH = 0;
+    fdas::harmonic_shape(N, K, H, &KH, &NH);
+    if (NH > 0 && (!sums_dev || !aligned(sums_dev, 4)))
+        return fail(FDAS_INVALID_ARG, "sums must be a 4-byte aligned device pointer");
+    const hipError_t e = fdas::launch_candidates(sums_dev, N, K, H, threshold, out_dev,
+                                                 capacity, count_dev, stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "candidates launch");
+    return ok();
+}
+
+}  // extern "C"

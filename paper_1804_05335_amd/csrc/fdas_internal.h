@@ -5,6 +5,8 @@
 #include <cstdint>
 #include <hip/hip_runtime.h>
 
+#include "../../include/fdas.h"
+
 namespace fdas {
 
 // Record `msg` as the calling thread's last-error text and return status.
@@ -52,5 +54,12 @@ hipError_t launch_backward(const float2* spec, int64_t N, const float2* bank, in
 int r2c_plan(int log2N, int bits[4]);
 hipError_t launch_r2c(const float* x, int log2n, float scale, float2* spec, float2* ws,
                       hipStream_t s);
+
+// Harmonic sums and candidates (fdas_harmonic.hip).
+void harmonic_shape(int64_t N, int K, int H, int* KH, int64_t* NH);
+hipError_t launch_harmonic_sum(const float* plane, int64_t N, int K, int H, const float* prev,
+                               float* out, hipStream_t s);
+hipError_t launch_candidates(const float* S, int64_t N, int K, int H, float threshold,
+                             fdas_candidate* out, int capacity, unsigned* count, hipStream_t s);
 
 }  // namespace fdas

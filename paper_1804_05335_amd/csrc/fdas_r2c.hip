@@ -142,13 +142,11 @@ __global__ __launch_bounds__(kR2cThreads) void r2c_pass_kernel(
         x[i1] = in[j + (int64_t)(RB * i1 + i2) * stride];
     // the tile's twiddles, while the loads are in flight; G <= NS, so the
     // tile's butterflies have the consecutive c = c0 .. c0 + G - 1
-#pragma unroll
     for (int m = t; m < R; m += kR2cThreads)
         wR[m] = root(m, S::logR);
     float2 u = make_float2(1.f, 0.f);
     if constexpr (!FIRST) {
         const int c0 = (int)(j0 & (NS - 1));
-#pragma unroll
         for (int idx = t; idx < 16 * G; idx += kR2cThreads)
             wA[idx] = root((int64_t)(c0 + idx % G) * (idx / G), log2NS + 4);
         u = root((int64_t)c * i2, log2NS + S::logR);
@@ -221,13 +219,10 @@ __global__ __launch_bounds__(2 * kR2cThreads, 4) void r2c_last_split_kernel(
 #pragma unroll
     for (int i1 = 0; i1 < 16; ++i1)
         x[i1] = in[c + (int64_t)(RB * i1 + i2) * NS];
-#pragma unroll
     for (int m = t; m < R; m += 2 * kR2cThreads)
         wR[m] = root(m, S::logR);
-#pragma unroll
     for (int m = t; m < 2 * R; m += 2 * kR2cThreads)
         w2R[m] = root(m, S::logR + 1);
-#pragma unroll
     for (int idx = t; idx < 2 * 16 * G; idx += 2 * kR2cThreads) {
         const int hh = idx / (16 * G), rem = idx % (16 * G);
         wA[idx] = root((int64_t)butterfly(hh, rem % G) * (rem / G), log2NS + 4);

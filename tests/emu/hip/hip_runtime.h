@@ -109,6 +109,7 @@ inline int emu_ds_bpermute(int addr, int data)
     __syncthreads();
     return v;
 }
+inline unsigned atomicAdd(unsigned* p, unsigned v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
 inline void sincospi(double x, double* s, double* c) { *s = std::sin(M_PI * x); *c = std::cos(M_PI * x); }
 
 typedef int hipError_t;

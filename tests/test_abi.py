@@ -210,3 +210,40 @@ def test_fourier2_validation_before_any_device_call():
         _lib.FDAS_INVALID_ARG
     assert L.fdas_correlate_fourier2_ex(p, 1000, p, p, 85, 256, 2048, p, -3, None) == \
         _lib.FDAS_INVALID_ARG
+
+
+def test_harmonic_validation_before_any_device_call():
+    L = _lib.lib()
+    kh, nh = ctypes.c_int(), ctypes.c_int64()
+    assert L.fdas_harmonic_shape(1000, 85, 4, ctypes.byref(kh), ctypes.byref(nh)) == _lib.FDAS_OK
+    assert (kh.value, nh.value) == (21, 250)
+    for N, K, H in ((1000, 84, 4), (1000, 85, 3), (1000, 85, 128), (-1, 85, 2), (1000, 0, 2),
+                    (1000, 4097, 2), ((1 << 32) + 1, 85, 2)):
+        assert L.fdas_harmonic_shape(N, K, H, ctypes.byref(kh), ctypes.byref(nh)) == \
+            _lib.FDAS_INVALID_ARG
+        assert L.fdas_harmonic_sum(_fake(0x1000), N, K, H, None, _fake(0x9000000), None) == \
+            _lib.FDAS_INVALID_ARG
+    assert L.fdas_harmonic_shape(1000, 85, 4, None, ctypes.byref(nh)) == _lib.FDAS_INVALID_ARG
+    plane, sums = _fake(0x10000000), _fake(0x20000000)
+    # NULL, misaligned, overlapping buffers, a previous fold for H = 1
+    assert L.fdas_harmonic_sum(None, 1000, 85, 4, None, sums, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_harmonic_sum(plane, 1000, 85, 4, None, _fake(0x20000002), None) == \
+        _lib.FDAS_INVALID_ARG
+    assert L.fdas_harmonic_sum(plane, 1000, 85, 4, None, _fake(0x10000000 + 4 * 1000),
+                               None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_harmonic_sum(plane, 1000, 85, 4, _fake(0x20000000 + 64), sums, None) == \
+        _lib.FDAS_INVALID_ARG
+    assert L.fdas_harmonic_sum(plane, 1000, 85, 1, sums, _fake(0x30000000), None) == \
+        _lib.FDAS_INVALID_ARG
+    # candidates: negative capacity, NULL / misaligned count or output
+    out, count = _fake(0x40000000), _fake(0x50000000)
+    assert L.fdas_find_candidates(sums, 1000, 85, 4, 1.0, out, -1, count, None) == \
+        _lib.FDAS_INVALID_ARG
+    assert L.fdas_find_candidates(sums, 1000, 85, 4, 1.0, out, 10, None, None) == \
+        _lib.FDAS_INVALID_ARG
+    assert L.fdas_find_candidates(sums, 1000, 85, 4, 1.0, _fake(0x40000004), 10, count,
+                                  None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_find_candidates(sums, 1000, 85, 4, 1.0, out, 10, _fake(0x50000002),
+                                  None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_find_candidates(None, 1000, 85, 4, 1.0, out, 10, count, None) == \
+        _lib.FDAS_INVALID_ARG

@@ -231,3 +231,69 @@ def test_emulated_fourier2(emu, L, M, N, zmax):
     _check_guards(buf, plane2)
     ref = direct.fourier_interpolated_power(A, zmax, 2.0, M)
     assert _rel(plane2, ref) < TOL
+
+
+def _emu_sum(emu, P, H, prev=None):
+    K, N = P.shape
+    kh, nh = ctypes.c_int(), ctypes.c_int64()
+    assert emu.fdas_harmonic_shape(ctypes.c_int64(N), K, H, ctypes.byref(kh),
+                                   ctypes.byref(nh)) == 0
+    buf, S = _guarded((kh.value, nh.value))
+    assert emu.fdas_harmonic_sum(_p(P), ctypes.c_int64(N), K, H,
+                                 _p(prev) if prev is not None else None, _p(S), None) == 0
+    _check_guards(buf, S)
+    return S.copy()
+
+
+@pytest.mark.parametrize("K,N", [(21, 300), (1, 37), (85, 1021), (7, 1)])
+def test_emulated_harmonic_sums_bitwise(emu, K, N):
+    # the FP32 sums in the order h = 1..H match the oracle bit for bit, built
+    # from scratch or on the previous fold
+    from oracle import harmonic as oh
+    P = syn.random_plane(5, K, N)
+    prev = P
+    for H in (1, 2, 4, 8, 16, 32):
+        ref = oh.harmonic_sum(P, H)
+        scratch = _emu_sum(emu, P, H)
+        assert np.array_equal(scratch, ref), H
+        if H >= 2:
+            chained = _emu_sum(emu, P, H, prev if H > 2 else None)
+            assert np.array_equal(chained, ref), H
+            prev = chained
+
+
+def _emu_candidates(emu, S_src, P, H, thr, capacity):
+    K, N = P.shape
+    out = np.zeros(max(capacity, 1) * 2 + 2 * 64, dtype=np.int64)   # 16-byte records + margins
+    out[:] = -7
+    view = out[64:64 + 2 * max(capacity, 1)]
+    count = np.full(1, 12345, dtype=np.uint32)
+    assert emu.fdas_find_candidates(_p(S_src), ctypes.c_int64(N), K, H, ctypes.c_float(thr),
+                                    _p(view), capacity, _p(count), None) == 0
+    assert np.all(out[:64] == -7) and np.all(out[64 + 2 * max(capacity, 1):] == -7)
+    rec = view.view(np.dtype([("r", "<i8"), ("row", "<i4"), ("power", "<f4")]))
+    return int(count[0]), rec[:min(int(count[0]), capacity)]
+
+
+@pytest.mark.parametrize("H", [1, 2, 8])
+def test_emulated_candidates_vs_oracle(emu, H):
+    from oracle import harmonic as oh
+    K, N = 41, 700
+    P = syn.random_plane(6, K, N)
+    S = oh.harmonic_sum(P, H)
+    thr = float(np.quantile(S, 0.97))
+    ref = oh.peaks(S, thr)
+    c = (K - 1) // 2
+    row0 = c - (S.shape[0] - 1) // 2
+    n, rec = _emu_candidates(emu, S, P, H, thr, 10000)
+    assert n == len(ref) > 0
+    got = sorted(zip(rec["row"] - row0, rec["r"]))
+    assert got == sorted(map(tuple, ref.tolist()))
+    assert np.array_equal(np.sort(rec["power"]), np.sort(S[ref[:, 0], ref[:, 1]]))
+    # a capacity below the count: the count stays exact, only that many are written
+    n2, rec2 = _emu_candidates(emu, S, P, H, thr, 5)
+    assert n2 == n and len(rec2) == 5
+    assert set(zip(rec2["row"] - row0, rec2["r"])) <= set(map(tuple, ref.tolist()))
+    # nothing above an unreachable threshold
+    n3, _ = _emu_candidates(emu, S, P, H, float(S.max()) + 1.0, 10)
+    assert n3 == 0

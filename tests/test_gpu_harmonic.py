@@ -1,0 +1,122 @@
+"""GPU parity of harmonic summing and peak candidates (Sec. 2 threshold,
+Sec. 3 harmonic summing and peak search) against the oracle.
+
+The sums are FP32 in the order h = 1..H on both sides, so they must agree
+bit for bit, chained on the previous fold or built from scratch, and the
+candidate sets must be identical -- on random planes up to the headline
+plane's size (85 x 2^21).  End to end, a pulsed accelerated signal in a
+time series goes through the real-to-complex front end, the correlation and
+the harmonic sums on the GPU and through the FP64 oracle's pipeline; the
+sums agree to 1e-5 of their peak and both find the signal's fundamental.
+"""
+import numpy as np
+import pytest
+
+import fdas_synth as syn
+from oracle import harmonic as oh
+from oracle import native, r2c
+from oracle import templates as ot
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FOLDS = (1, 2, 4, 8, 16, 32)
+
+
+@pytest.fixture(scope="module")
+def fd():
+    import paper_1804_05335_amd as f
+    f.lib()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return f
+
+
+def _from_scratch(fd, Pd, H):
+    K, N = Pd.shape
+    KH, NH = fd.fdas_harmonic_shape(N, K, H)
+    out = torch.full((KH, NH), float("nan"), dtype=torch.float32, device="cuda")
+    fd.fdas_harmonic_sum(Pd, N, K, H, None, out)
+    return out
+
+
+def _candidate_set(fd, S, N, K, H, thr):
+    r, row, power, n = fd.candidates(S, N, K, H, thr, capacity=1 << 20)
+    assert n == len(r)
+    c = (K - 1) // 2
+    row0 = c - (S.shape[0] - 1) // 2
+    return sorted(zip((row - row0).tolist(), r.tolist())), power
+
+
+@pytest.mark.parametrize("K,N", [(85, 65539), (201, 40000), (3, 5), (1, 1000)])
+def test_sums_bitwise_chained_and_from_scratch(fd, K, N):
+    P = syn.random_plane(11, K, N)
+    Pd = torch.from_numpy(P).cuda()
+    folds = fd.harmonic_sums(Pd, 32)
+    torch.cuda.synchronize()
+    for H, S in zip(FOLDS, folds):
+        ref = oh.harmonic_sum(P, H)
+        assert np.array_equal(S.cpu().numpy(), ref), H
+        assert np.array_equal(_from_scratch(fd, Pd, H).cpu().numpy(), ref), H
+
+
+@pytest.mark.parametrize("H", [1, 2, 4, 8, 16])
+def test_candidates_equal_the_oracle_set(fd, H):
+    K, N = 85, 65539
+    P = syn.random_plane(12, K, N)
+    S = oh.harmonic_sum(P, H)
+    thr = float(np.quantile(S, 0.995))
+    ref = sorted(map(tuple, oh.peaks(S, thr).tolist()))
+    got, power = _candidate_set(fd, torch.from_numpy(S).cuda(), N, K, H, thr)
+    assert len(ref) > 0 and got == ref
+    assert np.all(power > thr)
+
+
+def test_headline_plane_size(fd):
+    # 85 x 2^21, the plane of the headline correlation workload
+    K, N = 85, 1 << 21
+    P = syn.random_plane(13, K, N)
+    Pd = torch.from_numpy(P).cuda()
+    folds = fd.harmonic_sums(Pd, 32)
+    torch.cuda.synchronize()
+    for H, S in zip(FOLDS[1:], folds[1:]):
+        ref = oh.harmonic_sum(P, H)
+        assert np.array_equal(S.cpu().numpy(), ref), H
+        if H == 8:
+            thr = float(np.quantile(ref, 0.9999))
+            want = sorted(map(tuple, oh.peaks(ref, thr).tolist()))
+            got, _ = _candidate_set(fd, S, N, K, H, thr)
+            assert len(want) > 0 and got == want
+
+
+def test_pulsar_through_the_whole_path(fd):
+    # n = 2^17 samples, a pulsed signal with 8 equal harmonics at r0 =
+    # 2000.02 (harmonic h within 0.16 bin of h * 2000), z0 = 4 (harmonic 8 at
+    # z = 32 <= zmax = 40); 41 templates x 64 taps
+    n, r0, z0 = 1 << 17, 2000.02, 4.0
+    zmax, dz, M, L = 40.0, 2.0, 64, 512
+    x = syn.pulsed_series(3, n, r0, z0, 8, 0.02)
+    scale = 1.0 / np.sqrt(n)
+    N = n // 2
+    spec = fd.spectrum_from_series(torch.from_numpy(x).cuda(), scale)[:N].contiguous()
+    taps, bank = fd.make_bank(zmax, dz, M, L)
+    K = taps.shape[0]
+    plane = fd.correlate(spec, bank, K, M, L)
+    folds = fd.harmonic_sums(plane, 8)
+    torch.cuda.synchronize()
+    A = r2c.spectrum(x.astype(np.float64), scale)[:N]
+    Pref = native.power(A, ot.templates(zmax, dz, M))
+    c = (K - 1) // 2
+    for H, S in zip((1, 2, 4, 8), folds):
+        ref = oh.harmonic_sum_f64(Pref, H)
+        got = S.cpu().numpy()
+        assert np.max(np.abs(got - ref)) < 1e-5 * np.max(ref), H
+    S8 = folds[3].cpu().numpy()
+    kk, rr = np.unravel_index(np.argmax(S8), S8.shape)
+    row = c - c // 8 + kk
+    assert (row - c) * dz == z0 and rr == int(round(r0))
+    ref8 = oh.harmonic_sum_f64(Pref, 8)
+    assert np.unravel_index(np.argmax(ref8), ref8.shape) == (kk, rr)
+    # the 8-fold sum gathers several times the fundamental's own power
+    assert S8[kk, rr] > 4.0 * plane[row, rr].item()
+    r, rows, power, cnt = fd.candidates(folds[3], N, K, 8, 0.5 * float(S8[kk, rr]))
+    assert cnt >= 1 and np.any((rows == row) & (r == rr))
