@@ -383,8 +383,8 @@ typedef struct {
 } fdas_candidate;
 
 /*
- * Candidates of one fold (Sec. 2: the power is compared with a precomputed
- * threshold; Sec. 3: the search is for peaks): the points of S_H (sums_dev,
+ * Candidates of one fold (Sec. 3: the power is compared with a precomputed
+ * threshold, and the search is for peaks): the points of S_H (sums_dev,
  * [K_H][N_H] as fdas_harmonic_sum writes it for this N, K, H) whose value
  * exceeds `threshold` and is >= each of its up to 8 neighbours inside the
  * fold.  *count_dev (device unsigned) receives the number of such points;

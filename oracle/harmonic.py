@@ -2,11 +2,11 @@
 
 TEST INFRASTRUCTURE ONLY (see the package header).
 
-The paper names both steps without giving formulas (Sec. 2: the correlated
-power is compared with a precomputed threshold; Sec. 3: a pulsed signal
-spreads its power over harmonics, so the powers of the harmonics are added
-to that of the fundamental before the search for peaks; both steps lie
-outside the paper's measured path).  Readings used here:
+The paper names both steps without giving formulas (Sec. 3: the correlated
+power is compared with a precomputed threshold to find candidates; a pulsed
+signal spreads its power over harmonics, so the powers of the harmonics are
+added to that of the fundamental before the search for peaks; both steps
+lie outside the paper's measured path, Sec. 3 and Sec. 7).  Readings used here:
 
 Harmonic sum.  A constant-fdot signal at frequency bin r and drift z (Sec. 2:
 r = f T, z = fdot T^2) has its h-th harmonic at (h r, h z).  For a plane

@@ -170,7 +170,7 @@ def harmonic_sums(plane, max_fold: int):
 
 
 def candidates(sums, N: int, K: int, H: int, threshold: float, capacity: int = 1 << 16):
-    """Peaks of one fold above `threshold` (Sec. 2/3): (r int64, row int32,
+    """Peaks of one fold above `threshold` (Sec. 3): (r int64, row int32,
     power float32) host arrays sorted by (row, r), and the total count
     (which may exceed `capacity`; then only `capacity` are returned)."""
     import numpy as np

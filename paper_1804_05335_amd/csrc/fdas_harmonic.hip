@@ -1,7 +1,7 @@
 // Harmonic summing and peak candidates on the f-fdot power plane (Sec. 3:
 // a pulsed signal spreads its power over harmonics, whose powers are added
-// to the fundamental's before the search for peaks; Sec. 2: the power is
-// compared with a precomputed threshold).
+// to the fundamental's before the search for peaks, and the power is
+// compared with a precomputed threshold to find candidates).
 //
 // A constant-fdot signal at (r, z) has its h-th harmonic at (h r, h z).  On
 // a plane P[K][N] with rows z_k = (k - c) dz, c = (K - 1)/2, the H-fold sum

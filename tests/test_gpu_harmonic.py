@@ -1,5 +1,5 @@
-"""GPU parity of harmonic summing and peak candidates (Sec. 2 threshold,
-Sec. 3 harmonic summing and peak search) against the oracle.
+"""GPU parity of harmonic summing and peak candidates (Sec. 3: harmonic
+summing, threshold and peak search) against the oracle.
 
 The sums are FP32 in the order h = 1..H on both sides, so they must agree
 bit for bit, chained on the previous fold or built from scratch, and the

@@ -1,5 +1,5 @@
-"""Pins for the harmonic-sum and candidate oracle (Sec. 2 threshold, Sec. 3
-harmonic summing and peak search; readings in oracle/harmonic.py).
+"""Pins for the harmonic-sum and candidate oracle (Sec. 3: harmonic summing,
+threshold and peak search; readings in oracle/harmonic.py).
 
 Closed forms on planes linear in r and z fix which rows and columns are
 summed and how many terms; a planted harmonic comb must sum to its total at
