@@ -30,28 +30,51 @@ namespace {
 
 constexpr int kHarmThreads = 256;
 
-// One row of the H-fold sum per blockIdx.y, kHarmThreads columns per
-// blockIdx.x.  With prev (the H/2-fold, KHp x NHp), the sum starts from it
-// and adds harmonics H/2 + 1 .. H; without, it adds 1 .. H from zero.
+// One row of the H-fold sum per blockIdx.y, kHarmCols columns per
+// blockIdx.x: lane t takes columns t + kHarmThreads j, j < kHarmCols /
+// kHarmThreads, so each load instruction is coalesced and every lane keeps
+// several independent gathers in flight.  With prev (the H/2-fold, KHp x
+// NHp), the sum starts from it and adds harmonics H/2 + 1 .. H; without, it
+// adds 1 .. H from zero.
+constexpr int kHarmPerLane = 4;
+constexpr int kHarmCols = kHarmThreads * kHarmPerLane;
+
 __global__ __launch_bounds__(kHarmThreads) void harmonic_sum_kernel(
     const float* __restrict__ plane, int64_t N, int K, int H, const float* __restrict__ prev,
     int64_t NHp, int KHp, float* __restrict__ out, int64_t NH, int KH)
 {
-    const int64_t r = (int64_t)blockIdx.x * kHarmThreads + threadIdx.x;
-    if (r >= NH)
-        return;
+    const int64_t r0 = (int64_t)blockIdx.x * kHarmCols + threadIdx.x;
     const int c = (K - 1) / 2;
     const int krow = blockIdx.y;                       // row of the fold
     const int dk = krow - (KH - 1) / 2;                // k - c of the fundamental
-    float s = 0.f;
+    float s[kHarmPerLane];
+    bool in[kHarmPerLane];
+#pragma unroll
+    for (int j = 0; j < kHarmPerLane; ++j) {
+        in[j] = r0 + (int64_t)j * kHarmThreads < NH;
+        s[j] = 0.f;
+    }
     int h0 = 1;
     if (prev != nullptr) {
-        s = prev[(int64_t)(dk + (KHp - 1) / 2) * NHp + r];
+        const float* p = prev + (int64_t)(dk + (KHp - 1) / 2) * NHp + r0;
+#pragma unroll
+        for (int j = 0; j < kHarmPerLane; ++j)
+            if (in[j])
+                s[j] = p[(int64_t)j * kHarmThreads];
         h0 = H / 2 + 1;
     }
-    for (int h = h0; h <= H; ++h)
-        s += plane[(int64_t)(c + h * dk) * N + (int64_t)h * r];
-    out[(int64_t)krow * NH + r] = s;
+    for (int h = h0; h <= H; ++h) {
+        const float* row = plane + (int64_t)(c + h * dk) * N + (int64_t)h * r0;
+#pragma unroll
+        for (int j = 0; j < kHarmPerLane; ++j)
+            if (in[j])
+                s[j] += row[(int64_t)h * j * kHarmThreads];
+    }
+    float* o = out + (int64_t)krow * NH + r0;
+#pragma unroll
+    for (int j = 0; j < kHarmPerLane; ++j)
+        if (in[j])
+            o[(int64_t)j * kHarmThreads] = s[j];
 }
 
 __global__ void zero_count_kernel(unsigned* __restrict__ count)
@@ -115,7 +138,7 @@ hipError_t launch_harmonic_sum(const float* plane, int64_t N, int K, int H, cons
         harmonic_shape(N, K, H / 2, &KHp, &NHp);
     if (NH == 0)
         return hipSuccess;
-    const dim3 grid((unsigned)((NH + kHarmThreads - 1) / kHarmThreads), (unsigned)KH);
+    const dim3 grid((unsigned)((NH + kHarmCols - 1) / kHarmCols), (unsigned)KH);
     hipLaunchKernelGGL(harmonic_sum_kernel, grid, dim3(kHarmThreads), 0, s, plane, N, K, H, prev,
                        NHp, KHp, out, NH, KH);
     return hipGetLastError();
