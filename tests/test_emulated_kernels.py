@@ -297,3 +297,8 @@ def test_emulated_candidates_vs_oracle(emu, H):
     # nothing above an unreachable threshold
     n3, _ = _emu_candidates(emu, S, P, H, float(S.max()) + 1.0, 10)
     assert n3 == 0
+    # count only: capacity 0 and no output buffer
+    count = np.full(1, 99, dtype=np.uint32)
+    assert emu.fdas_find_candidates(_p(S), ctypes.c_int64(N), K, H, ctypes.c_float(thr), None, 0,
+                                    _p(count), None) == 0
+    assert int(count[0]) == n
