@@ -184,3 +184,29 @@ def candidates(sums, N: int, K: int, H: int, threshold: float, capacity: int = 1
     order = np.lexsort((rec["r"], rec["row"]))
     rec = rec[order]
     return rec["r"].copy(), rec["row"].copy(), rec["power"].copy(), n
+
+
+def search(x, zmax: float, dz: float, M: int, L: int, max_fold: int, thresholds,
+           capacity: int = 1 << 16):
+    """The search path of Sec. 3 on one device time series: real-to-complex
+    transform (scaled by 1/sqrt(n), so white noise of unit variance gives
+    unit mean power), the f-fdot plane, harmonic sums up to ``max_fold``
+    and the peaks of each fold above ``thresholds[H]`` (a dict keyed by the
+    fold, 1 = the plane itself; folds without a threshold are skipped).
+    Returns {H: (r, row, power, count)} with the candidates of each fold as
+    host arrays sorted by (row, r); the fundamental's drift is
+    z = (row - (K - 1)/2) dz.  Every step runs in the library's kernels."""
+    n = x.numel()
+    N = n // 2
+    spec = spectrum_from_series(x, 1.0 / float(n) ** 0.5)[:N].contiguous()
+    taps, bank = make_bank(zmax, dz, M, L, device=x.device)
+    K = taps.shape[0]
+    plane = correlate(spec, bank, K, M, L)
+    folds = harmonic_sums(plane, max_fold)
+    out = {}
+    H = 1
+    for S in folds:
+        if H in thresholds:
+            out[H] = candidates(S, N, K, H, float(thresholds[H]), capacity)
+        H *= 2
+    return out

@@ -120,3 +120,17 @@ def test_pulsar_through_the_whole_path(fd):
     assert S8[kk, rr] > 4.0 * plane[row, rr].item()
     r, rows, power, cnt = fd.candidates(folds[3], N, K, 8, 0.5 * float(S8[kk, rr]))
     assert cnt >= 1 and np.any((rows == row) & (r == rr))
+
+
+def test_search_path_finds_the_pulsar(fd):
+    # the same pulsed signal through the library's one-call search path
+    n, r0, z0 = 1 << 17, 2000.02, 4.0
+    x = torch.from_numpy(syn.pulsed_series(3, n, r0, z0, 8, 0.02)).cuda()
+    res = fd.search(x, 40.0, 2.0, 64, 512, 8, {1: 15.0, 8: 60.0})
+    r, row, power, cnt = res[8]
+    K = 41
+    c = (K - 1) // 2
+    assert cnt >= 1 and np.any((row == c + int(z0 / 2.0)) & (r == int(round(r0))))
+    best = np.argmax(power)
+    assert (row[best] - c) * 2.0 == z0 and r[best] == int(round(r0))
+    assert set(res) == {1, 8}
