@@ -7,6 +7,11 @@
  * a bank of K complex FIR templates, one per trial frequency derivative z,
  * by overlap-save FFT segments, and the |.|^2 f-fdot power plane is
  * written out (Sec. 3, Fig. 1 and Fig. 3 caption; Sec. 4.1 workflow).
+ * Around it: the batched path and its autotuner, the adjoint, interbinning,
+ * two-bin Fourier interpolation, a half-size (+-z symmetric) bank, the
+ * real-to-complex front end that makes the spectrum from a time series, and
+ * harmonic summing with peak candidates on the plane (Sec. 3 processing
+ * steps).
  *
  * Definition of the result (Sec. 2, eq. 23): with taps j in [0, M) at bin
  * offsets e_j = j - M/2 and the spectrum A taken as zero outside [0, N),
