@@ -134,3 +134,50 @@ def test_search_path_finds_the_pulsar(fd):
     best = np.argmax(power)
     assert (row[best] - c) * 2.0 == z0 and r[best] == int(round(r0))
     assert set(res) == {1, 8}
+
+
+def test_graph_capture_and_replay(fd):
+    # folds 2..8 and the candidates of fold 8 captured once, replayed on new
+    # planes written in place; every replay equals the eager calls
+    K, N = 41, 50000
+    planes = [syn.random_plane(s, K, N) for s in (21, 22, 23)]
+    Pd = torch.from_numpy(planes[0]).cuda()
+    shapes = [fd.fdas_harmonic_shape(N, K, H) for H in (2, 4, 8)]
+    outs = [torch.empty(s, dtype=torch.float32, device="cuda") for s in shapes]
+    cap = 4096
+    cbuf = torch.empty(cap * 16, dtype=torch.uint8, device="cuda")
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    thr = 12.0
+
+    def run():
+        fd.fdas_harmonic_sum(Pd, N, K, 2, None, outs[0])
+        fd.fdas_harmonic_sum(Pd, N, K, 4, outs[0], outs[1])
+        fd.fdas_harmonic_sum(Pd, N, K, 8, outs[1], outs[2])
+        fd.fdas_find_candidates(outs[2], N, K, 8, thr, cbuf, cap, count)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
+    for P in planes[1:] + planes[:1]:
+        Pd.copy_(torch.from_numpy(P))
+        for o in outs:
+            o.fill_(float("nan"))
+        count.fill_(-1)
+        g.replay()
+        torch.cuda.synchronize()
+        got = [o.cpu().numpy() for o in outs]
+        n_graph = int(count.item())
+        run()                                   # eager, same buffers
+        torch.cuda.synchronize()
+        for a, o in zip(got, outs):
+            assert np.array_equal(a, o.cpu().numpy())
+        assert n_graph == int(count.item()) and n_graph > 0
+        ref = oh.harmonic_sum(P, 8)
+        assert np.array_equal(got[2], ref)
+        assert n_graph == len(oh.peaks(ref, thr))
