@@ -361,7 +361,9 @@ int fdas_r2c(const float *x_dev, int64_t n, float scale, fdas_cf32 *spec_dev, vo
  * [0, N_H), N_H = ceil(N/H), and |k - c| <= floor(c/H), i.e. K_H =
  * 2 floor(c/H) + 1 rows; S_H is stored [K_H][N_H] row-major, its row i
  * being plane row c - floor(c/H) + i.  The sum is formed in FP32 in the
- * order h = 1..H.
+ * order h = 1..H.  The columns may be of any uniform resolution: the
+ * interbinned or two-bin plane ([K][2N], half bins) is summed as a plane of
+ * 2N columns.
  */
 
 /* K_H and N_H of the H-fold sum (K odd in [1, 4096], H a power of two in
