@@ -441,7 +441,8 @@ struct Geometry {
 // Values per lane of the adjoint, which keeps five transform-sized arrays
 // live (window, accumulator, work array, two bank rows): 8 from L = 512 on,
 // 16 at L = 8192 so a workgroup stays at 512 lanes.  kMinWaves is the
-// occupancy (waves per SIMD) the register allocation is held to.
+// occupancy (waves per SIMD) the register allocation is held to, with both
+// gradients; kMinWavesSpec with the spectrum gradient only.
 #ifndef FDAS_BWD_WAVES
 #define FDAS_BWD_WAVES 2
 #endif
@@ -452,6 +453,8 @@ template <int L>
 struct BwdGeometry {
     static constexpr int E = L <= 256 ? 4 : (L >= 8192 ? FDAS_BWD_E8192 : 8);
     static constexpr int kMinWaves = L >= 8192 ? 1 : FDAS_BWD_WAVES;
+    // spectrum gradient only: no taps transform, fits 168 VGPRs up to L = 2048
+    static constexpr int kMinWavesSpec = L >= 8192 ? 1 : (L >= 4096 ? FDAS_BWD_WAVES : 3);
 };
 
 }  // namespace fdas

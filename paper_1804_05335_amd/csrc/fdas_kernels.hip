@@ -445,11 +445,14 @@ struct Bwd {
     // template the weights w_z are loaded before the inverse transform and
     // the next bank row is loaded once the first pass of FFT(g) has started,
     // so neither load's latency sits on the critical path; row z stays live
-    // for the accumulate step.
+    // for the accumulate step.  WANT_T is a compile-time switch: without the
+    // taps gradient's transform the kernel needs ~80 fewer VGPRs, which buys
+    // a third wave per SIMD.
+    template <bool WANT_T>
     __device__ static void item(const float2* __restrict__ spec, int64_t N,
                                 const float2* __restrict__ bank, int M, int64_t s, int z0,
                                 int z1, const float* __restrict__ dLdP, bool want_A,
-                                bool want_T, float2* __restrict__ partA,
+                                float2* __restrict__ partA,
                                 float2* __restrict__ partT, const float2 (&tw)[NTW],
                                 float2*& la, float2*& lb, int t, float2 (&Hc)[E])
     {
@@ -490,7 +493,7 @@ struct Bwd {
                     acc[m].y = fmaf(v[m].y, Hc[m].x, fmaf(-v[m].x, Hc[m].y, acc[m].y));
                 }
             }
-            if (want_T) {
+            if constexpr (WANT_T) {
                 F::template run_mul<true, kMulConj>(X, v, v, la, lb, tw, t);  // IFFT(X conj(G))
                 float2* pz = partT + (int64_t)z * M;
 #pragma unroll
@@ -515,10 +518,11 @@ struct Bwd {
     }
 };
 
-template <int L>
-__global__ __launch_bounds__(Bwd<L>::T, BwdGeometry<L>::kMinWaves) void backward_kernel(
+template <int L, bool WANT_T>
+__global__ __launch_bounds__(Bwd<L>::T, WANT_T ? BwdGeometry<L>::kMinWaves
+                                               : BwdGeometry<L>::kMinWavesSpec) void backward_kernel(
     const float2* __restrict__ spec, int64_t N, const float2* __restrict__ bank, int K, int M,
-    int zchunk, int64_t nwin, const float* __restrict__ dLdP, int want_A, int want_T,
+    int zchunk, int64_t nwin, const float* __restrict__ dLdP, int want_A,
     float2* __restrict__ partA, float2* __restrict__ partT)
 {
     using Bk = Bwd<L>;
@@ -534,8 +538,9 @@ __global__ __launch_bounds__(Bwd<L>::T, BwdGeometry<L>::kMinWaves) void backward
     const int z1 = min(K, z0 + zchunk);
     float2 H[Bk::E];
     Bk::W::load_row(H, bank, z0, t);
-    Bk::item(spec, N, bank, M, s, z0, z1, dLdP, want_A != 0, want_T != 0,
-             partA + ((int64_t)c * nwin + s) * L, partT + s * (int64_t)K * M, tw, la, lb, t, H);
+    Bk::template item<WANT_T>(spec, N, bank, M, s, z0, z1, dLdP, want_A != 0,
+                              partA + ((int64_t)c * nwin + s) * L, partT + s * (int64_t)K * M, tw,
+                              la, lb, t, H);
 }
 
 // grad_A[k] = sum over chunks c and windows s covering k of
@@ -750,9 +755,13 @@ static hipError_t launch_backward_L(const float2* spec, int64_t N, const float2*
                                    hipStream_t s)
 {
     const int nzc = (K + zchunk - 1) / zchunk;
-    hipLaunchKernelGGL(backward_kernel<L>, dim3((unsigned)nwin, (unsigned)nzc), dim3(Bwd<L>::T),
-                       0, s, spec, N, bank, K, M, zchunk, nwin, dLdP, want_A, want_T, partA,
-                       partT);
+    const dim3 grid((unsigned)nwin, (unsigned)nzc);
+    if (want_T)
+        hipLaunchKernelGGL((backward_kernel<L, true>), grid, dim3(Bwd<L>::T), 0, s, spec, N, bank,
+                           K, M, zchunk, nwin, dLdP, want_A, partA, partT);
+    else
+        hipLaunchKernelGGL((backward_kernel<L, false>), grid, dim3(Bwd<L>::T), 0, s, spec, N,
+                           bank, K, M, zchunk, nwin, dLdP, want_A, partA, partT);
     return hipGetLastError();
 }
 

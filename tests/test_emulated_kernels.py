@@ -145,6 +145,12 @@ def test_emulated_backward_vs_oracle(emu, L, M, N):
     rA, rT = native.grads(A, taps, w)
     assert _rel(gA, rA) < TOL
     assert _rel(gT, rT) < TOL
+    # the spectrum gradient alone (the kernel specialised without the taps
+    # transform) is bitwise the one computed beside the taps gradient
+    gA2 = np.full(N, np.nan, dtype=np.complex64)
+    assert emu.fdas_correlate_backward(_p(A), ctypes.c_int64(N), _p(bank), K, M, L, _p(w),
+                                       _p(gA2), None, wsp, ctypes.c_size_t(wsb), None) == 0
+    assert np.array_equal(gA2, gA)
 
 
 @pytest.mark.parametrize("L,M,N,grid", [(256, 32, 1000, 0), (512, 64, 449, 3), (2048, 256, 1793, 0),
