@@ -73,8 +73,8 @@ const char *fdas_last_error(void);
  * Number of trial templates for the z grid z_k = (k - (K-1)/2) * dz,
  * k in [0, K), i.e. -zmax .. +zmax in steps of dz, K = 2*zmax/dz + 1.
  * zmax >= 0, dz > 0 and zmax must be an integer multiple of dz (relative
- * tolerance 1e-9), else FDAS_INVALID_ARG.  The paper's grid steps z by 2
- * ("one template", Sec. 5.2).
+ * tolerance 1e-9), else FDAS_INVALID_ARG.  The paper's grid steps z by 2,
+ * one template apart (Sec. 5.2).
  */
 int fdas_num_templates(double zmax, double dz, int *K);
 
