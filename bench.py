@@ -216,9 +216,67 @@ def bench_batched(fdas, torch, steps: int):
            "plain_loop_ms": ms_p, "plain_loop_points_per_s": pts / ms_p * 1e3,
            "speedup_batched_vs_plain": ms_p / ms_b,
            "segment_autotuned": L, "autotune_trials_ms": tuned_ms}
-    del specs, planes, ws
+    del ws
+    out["harmonic"] = _batched_harmonic(fdas, torch, planes, offs, o, K, steps)
+    del specs, planes
     torch.cuda.empty_cache()
     return out
+
+
+def _batched_harmonic(fdas, torch, planes, offs, o, K, steps):
+    """Folds 2..32 of all the batch's planes: one launch per fold for every
+    spectrum against a loop of single-spectrum calls writing the same
+    layout, plus the 32-fold candidates of every spectrum."""
+    nspec = len(o) - 1
+    folds = [2, 4, 8, 16, 32]
+    pres, outs = [], []
+    for H in folds:
+        KH, _ = fdas.fdas_harmonic_shape(0, K, H)
+        pre = fdas.fold_prefix(o, H)
+        pres.append((KH, pre))
+        outs.append(torch.empty(KH * int(pre[-1]), dtype=torch.float32, device="cuda"))
+    hws = torch.empty(fdas.fdas_harmonic_batched_workspace_bytes(nspec), dtype=torch.uint8,
+                      device="cuda")
+
+    def batched():
+        for i, H in enumerate(folds):
+            fdas.fdas_harmonic_sum_batched(planes, offs, nspec, K, H, outs[i - 1] if i else None,
+                                           outs[i], hws)
+
+    def loop():
+        for b in range(nspec):
+            n = int(o[b + 1] - o[b])
+            if n <= 0:
+                continue
+            pl = planes[K * o[b]:K * o[b + 1]]
+            for i, H in enumerate(folds):
+                KH, pre = pres[i]
+                dst = outs[i][KH * pre[b]:KH * pre[b + 1]]
+                src = None
+                if i:
+                    KHp, prep = pres[i - 1]
+                    src = outs[i - 1][KHp * prep[b]:KHp * prep[b + 1]]
+                fdas.fdas_harmonic_sum(pl, n, K, H, src, dst)
+
+    batched()
+    ms_b = _timed(torch, batched, max(2, steps // 2))
+    loop()
+    ms_l = _timed(torch, loop, max(2, steps // 2))
+    cap = 1 << 16
+    cbuf = torch.empty(cap * 16, dtype=torch.uint8, device="cuda")
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    thr = 80.0
+
+    def cands():
+        fdas.fdas_find_candidates_batched(outs[-1], offs, nspec, K, 32, thr, cbuf, cap, count, hws)
+
+    cands()
+    ms_c = _timed(torch, cands, max(2, steps // 2))
+    res = {"folds": "2..32, each on the previous one", "batched_ms": ms_b, "loop_ms": ms_l,
+           "speedup_batched_vs_loop": ms_l / ms_b,
+           "candidates_32fold": {"threshold": thr, "count": int(count.item()), "ms": ms_c}}
+    del outs, cbuf, hws
+    return res
 
 
 def bench_fwd_bwd(fdas, torch, steps: int):

@@ -404,6 +404,34 @@ int fdas_find_candidates(const float *sums_dev, int64_t N, int K, int H, float t
                          fdas_candidate *out_dev, int capacity, unsigned *count_dev,
                          hipStream_t stream);
 
+/*
+ * The same over the planes of fdas_correlate_batched (plane b at
+ * planes_dev + K * offsets[b], [K][N_b]; offsets_dev the same device array,
+ * read at execution time), every spectrum in one launch.  Fold H of
+ * spectrum b is stored at sums_dev + K_H * C_H[b] as [K_H][ceil(N_b/H)],
+ * with C_H[b] = sum_{b' < b} ceil(N_b'/H) (empty spectra contribute
+ * nothing), so sums_dev holds K_H * C_H[nspec] floats; prev_dev (or NULL)
+ * is the H/2-fold in the same layout.  ws_dev: at least
+ * fdas_harmonic_batched_workspace_bytes(nspec) bytes (8-byte aligned,
+ * scratch).  Bitwise equal to fdas_harmonic_sum on each spectrum.  No host
+ * wait, allocation or memset: capturable in a graph.
+ */
+size_t fdas_harmonic_batched_workspace_bytes(int nspec);
+int fdas_harmonic_sum_batched(const float *planes_dev, const int64_t *offsets_dev, int nspec,
+                              int K, int H, const float *prev_dev, float *sums_dev, void *ws_dev,
+                              size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Candidates of fold H of every spectrum (sums_dev as written by
+ * fdas_harmonic_sum_batched for the same offsets, K, H), as
+ * fdas_find_candidates; a record's r is the packed bin index offsets[b] + r,
+ * which also names the spectrum.  ws_dev as above.
+ */
+int fdas_find_candidates_batched(const float *sums_dev, const int64_t *offsets_dev, int nspec,
+                                 int K, int H, float threshold, fdas_candidate *out_dev,
+                                 int capacity, unsigned *count_dev, void *ws_dev,
+                                 size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,8 @@ from ._lib import (FdasError, fdas_backward_workspace_bytes, fdas_bank_elems,  #
                    fdas_bank_sym_elems, fdas_correlate_sym, fdas_correlate_sym_ex,
                    fdas_prepare_bank_sym, fdas_make_templates_half, fdas_correlate_fourier2,
                    fdas_correlate_fourier2_ex, fdas_harmonic_shape, fdas_harmonic_sum,
-                   fdas_find_candidates, lib)
+                   fdas_find_candidates, fdas_harmonic_batched_workspace_bytes,
+                   fdas_harmonic_sum_batched, fdas_find_candidates_batched, lib)
 
 
 def make_bank(zmax: float, dz: float, M: int, L: int, device="cuda"):
@@ -210,3 +211,60 @@ def search(x, zmax: float, dz: float, M: int, L: int, max_fold: int, thresholds,
             out[H] = candidates(S, N, K, H, float(thresholds[H]), capacity)
         H *= 2
     return out
+
+
+def fold_prefix(offsets_host, H: int):
+    """C_H[b] = sum_{b' < b} ceil(N_b'/H) for packed-bin offsets (host int64
+    array of nspec + 1): fold H of spectrum b starts at K_H * C_H[b]."""
+    import numpy as np
+    lens = np.maximum(np.diff(np.asarray(offsets_host, dtype=np.int64)), 0)
+    pre = np.zeros(len(lens) + 1, dtype=np.int64)
+    np.cumsum((lens + H - 1) // H, out=pre[1:])
+    return pre
+
+
+def harmonic_sums_batched(planes, offsets, K: int, max_fold: int):
+    """Folds 2, 4, .., max_fold of the planes of correlate_batched (flat
+    float32 device tensor; offsets the int64 device tensor of nspec + 1
+    packed-bin offsets), each fold built on the previous one in one launch
+    for all spectra.  Returns the list [planes, S_2, S_4, ...] of flat
+    tensors; fold H of spectrum b is S_H[K_H C_H[b] : K_H C_H[b+1]] viewed
+    as [K_H][ceil(N_b/H)] (see fold_prefix)."""
+    import torch
+    offs = offsets.cpu().numpy()
+    nspec = len(offs) - 1
+    ws = torch.empty(max(fdas_harmonic_batched_workspace_bytes(nspec), 1), dtype=torch.uint8,
+                     device=planes.device)
+    folds = [planes]
+    H = 2
+    while H <= max_fold:
+        KH, _ = fdas_harmonic_shape(0, K, H)
+        total = int(fold_prefix(offs, H)[-1])
+        out = torch.empty(max(KH * total, 1), dtype=torch.float32, device=planes.device)
+        fdas_harmonic_sum_batched(planes, offsets, nspec, K, H, folds[-1] if H > 2 else None,
+                                  out, ws)
+        folds.append(out)
+        H *= 2
+    return folds
+
+
+def candidates_batched(sums, offsets, K: int, H: int, threshold: float, capacity: int = 1 << 16):
+    """Peaks above `threshold` of fold H of every spectrum: (spectrum int64,
+    r int64, row int32, power float32) host arrays sorted by (spectrum, row,
+    r), and the total count."""
+    import numpy as np
+    import torch
+    nspec = offsets.numel() - 1
+    ws = torch.empty(max(fdas_harmonic_batched_workspace_bytes(nspec), 1), dtype=torch.uint8,
+                     device=sums.device)
+    out = torch.empty(max(capacity, 1) * 16, dtype=torch.uint8, device=sums.device)
+    count = torch.zeros(1, dtype=torch.int32, device=sums.device)
+    fdas_find_candidates_batched(sums, offsets, nspec, K, H, threshold, out, capacity, count, ws)
+    n = int(count.item())
+    rec = np.frombuffer(out.cpu().numpy().tobytes(), dtype=np.dtype(
+        [("r", "<i8"), ("row", "<i4"), ("power", "<f4")]))[:min(n, capacity)]
+    offs = offsets.cpu().numpy()
+    spec = np.searchsorted(offs, rec["r"], side="right") - 1
+    r = rec["r"] - offs[spec]
+    order = np.lexsort((r, rec["row"], spec))
+    return spec[order], r[order], rec["row"][order].copy(), rec["power"][order].copy(), n

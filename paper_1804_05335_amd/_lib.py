@@ -62,6 +62,10 @@ SIGNATURES = [
     ("fdas_harmonic_shape", _I, [_I64, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I64)]),
     ("fdas_harmonic_sum", _I, [_P, _I64, _I, _I, _P, _P, _P]),
     ("fdas_find_candidates", _I, [_P, _I64, _I, _I, ctypes.c_float, _P, _I, _P, _P]),
+    ("fdas_harmonic_batched_workspace_bytes", _SZ, [_I]),
+    ("fdas_harmonic_sum_batched", _I, [_P, _P, _I, _I, _I, _P, _P, _P, _SZ, _P]),
+    ("fdas_find_candidates_batched", _I, [_P, _P, _I, _I, _I, ctypes.c_float, _P, _I, _P, _P,
+                                          _SZ, _P]),
 ]
 
 # fdas_candidate: {int64 r; int32 row; float power} (16 bytes)
@@ -386,3 +390,39 @@ def fdas_find_candidates(sums, N: int, K: int, H: int, threshold: float, out, ca
     _check(lib().fdas_find_candidates(_ptr(sums), N, K, H, threshold, _ptr(out), capacity,
                                       _ptr(count), _stream(stream, sums)),
            "fdas_find_candidates")
+
+
+def fdas_harmonic_batched_workspace_bytes(nspec: int) -> int:
+    return int(lib().fdas_harmonic_batched_workspace_bytes(nspec))
+
+
+def fdas_harmonic_sum_batched(planes, offsets, nspec: int, K: int, H: int, prev, sums, ws,
+                              stream=None) -> None:
+    """offsets: int64 device tensor of nspec + 1 packed-bin offsets; sizes
+    of planes / prev / sums are the caller's (they follow from the host
+    copy of the offsets)."""
+    import torch
+    _require(planes, torch.float32, "planes")
+    _require(offsets, torch.int64, "offsets", nspec + 1)
+    if prev is not None:
+        _require(prev, torch.float32, "prev")
+    _require(sums, torch.float32, "sums")
+    _require(ws, torch.uint8, "ws", fdas_harmonic_batched_workspace_bytes(nspec))
+    _check(lib().fdas_harmonic_sum_batched(_ptr(planes), _ptr(offsets), nspec, K, H, _ptr(prev),
+                                           _ptr(sums), _ptr(ws), ws.numel(),
+                                           _stream(stream, planes)),
+           "fdas_harmonic_sum_batched")
+
+
+def fdas_find_candidates_batched(sums, offsets, nspec: int, K: int, H: int, threshold: float,
+                                 out, capacity: int, count, ws, stream=None) -> None:
+    import torch
+    _require(sums, torch.float32, "sums")
+    _require(offsets, torch.int64, "offsets", nspec + 1)
+    _require(out, torch.uint8, "out", capacity * CANDIDATE_BYTES)
+    _require(count, torch.int32, "count", 1)
+    _require(ws, torch.uint8, "ws", fdas_harmonic_batched_workspace_bytes(nspec))
+    _check(lib().fdas_find_candidates_batched(_ptr(sums), _ptr(offsets), nspec, K, H, threshold,
+                                              _ptr(out), capacity, _ptr(count), _ptr(ws),
+                                              ws.numel(), _stream(stream, sums)),
+           "fdas_find_candidates_batched")

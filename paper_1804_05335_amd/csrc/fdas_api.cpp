@@ -718,3 +718,91 @@ int fdas_find_candidates(const float* sums_dev, int64_t N, int K, int H, float t
 }
 
 }  // extern "C"
+
+extern "C" {
+
+size_t fdas_harmonic_batched_workspace_bytes(int nspec)
+{
+    if (nspec < 0 || nspec > kMaxSpectra)
+        return 0;
+    const size_t b = 2 * ((size_t)nspec + 1) * sizeof(int64_t);
+    return (b + 255) & ~(size_t)255;
+}
+
+namespace {
+
+int check_harmonic_batched(const int64_t* offsets_dev, int nspec, int K, int H, void* ws_dev,
+                           size_t ws_bytes)
+{
+    const int st = check_harmonic(0, K, H);
+    if (st)
+        return st;
+    if (nspec < 0 || nspec > kMaxSpectra)
+        return fail(FDAS_INVALID_ARG, "nspec = %d outside [0, %d]", nspec, kMaxSpectra);
+    if (nspec == 0)
+        return FDAS_OK;
+    if (!offsets_dev || !ws_dev || !aligned(offsets_dev, 8) || !aligned(ws_dev, 8))
+        return fail(FDAS_INVALID_ARG, "offsets and ws must be 8-byte aligned device pointers");
+    if (ws_bytes < fdas_harmonic_batched_workspace_bytes(nspec))
+        return fail(FDAS_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", ws_bytes,
+                    fdas_harmonic_batched_workspace_bytes(nspec));
+    return FDAS_OK;
+}
+
+}  // namespace
+
+int fdas_harmonic_sum_batched(const float* planes_dev, const int64_t* offsets_dev, int nspec,
+                              int K, int H, const float* prev_dev, float* sums_dev, void* ws_dev,
+                              size_t ws_bytes, hipStream_t stream)
+{
+    const int st = check_harmonic_batched(offsets_dev, nspec, K, H, ws_dev, ws_bytes);
+    if (st)
+        return st;
+    if (prev_dev && H < 2)
+        return fail(FDAS_INVALID_ARG, "a previous fold needs H >= 2");
+    if (nspec == 0)
+        return ok();
+    if (!planes_dev || !sums_dev || !aligned(planes_dev, 4) || !aligned(sums_dev, 4) ||
+        (prev_dev && !aligned(prev_dev, 4)))
+        return fail(FDAS_INVALID_ARG, "planes and sums must be 4-byte aligned device pointers");
+    auto* pre = static_cast<int64_t*>(ws_dev);
+    const hipError_t e = fdas::launch_harmonic_batched(planes_dev, offsets_dev, nspec, K, H,
+                                                       prev_dev, sums_dev, pre, pre + nspec + 1,
+                                                       stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "batched harmonic sum launch");
+    return ok();
+}
+
+int fdas_find_candidates_batched(const float* sums_dev, const int64_t* offsets_dev, int nspec,
+                                 int K, int H, float threshold, fdas_candidate* out_dev,
+                                 int capacity, unsigned* count_dev, void* ws_dev,
+                                 size_t ws_bytes, hipStream_t stream)
+{
+    const int st = check_harmonic_batched(offsets_dev, nspec, K, H, ws_dev, ws_bytes);
+    if (st)
+        return st;
+    if (capacity < 0)
+        return fail(FDAS_INVALID_ARG, "capacity = %d must be >= 0", capacity);
+    if (!count_dev || !aligned(count_dev, 4))
+        return fail(FDAS_INVALID_ARG, "count must be a 4-byte aligned device pointer");
+    if (capacity > 0 && (!out_dev || !aligned(out_dev, 8)))
+        return fail(FDAS_INVALID_ARG, "out must be an 8-byte aligned device pointer");
+    if (nspec > 0 && (!sums_dev || !aligned(sums_dev, 4)))
+        return fail(FDAS_INVALID_ARG, "sums must be a 4-byte aligned device pointer");
+    if (nspec == 0) {
+        // still a defined count: zero
+        const hipError_t e = fdas::launch_candidates(nullptr, 0, K, H, threshold, out_dev,
+                                                     capacity, count_dev, stream);
+        return e == hipSuccess ? ok() : hip_fail(e, "candidates launch");
+    }
+    auto* pre = static_cast<int64_t*>(ws_dev);
+    const hipError_t e = fdas::launch_candidates_batched(sums_dev, offsets_dev, nspec, K, H,
+                                                         threshold, out_dev, capacity, count_dev,
+                                                         pre, pre + nspec + 1, stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "batched candidates launch");
+    return ok();
+}
+
+}  // extern "C"

@@ -61,5 +61,15 @@ hipError_t launch_harmonic_sum(const float* plane, int64_t N, int K, int H, cons
                                float* out, hipStream_t s);
 hipError_t launch_candidates(const float* S, int64_t N, int K, int H, float threshold,
                              fdas_candidate* out, int capacity, unsigned* count, hipStream_t s);
+// Batched folds / candidates over the planes of fdas_correlate_batched;
+// colpre and prevpre ([nspec + 1] int64 each) hold the fold column prefix
+// sums for H and H/2.
+hipError_t launch_harmonic_batched(const float* planes, const int64_t* offsets, int nspec, int K,
+                                   int H, const float* prev, float* sums, int64_t* colpre,
+                                   int64_t* prevpre, hipStream_t s);
+hipError_t launch_candidates_batched(const float* sums, const int64_t* offsets, int nspec, int K,
+                                     int H, float threshold, fdas_candidate* out, int capacity,
+                                     unsigned* count, int64_t* colpre, int64_t* prevpre,
+                                     hipStream_t s);
 
 }  // namespace fdas

@@ -17,8 +17,11 @@ def build() -> str:
                                                   "fdas_r2c.hip", "fdas_harmonic.hip")]
     tmp = OUT + f".tmp{os.getpid()}"
     # clang (ROCm's, as a host compiler): the kernels use clang vector types
+    # a small persistent grid for the batched harmonic kernels: every
+    # emulated workgroup is a set of host threads
     cmd = [CXX, "-O2", "-std=c++20", "-fPIC", "-shared", "-pthread", "-I", HERE,
-           "-I", os.path.join(ROOT, "include"), "-x", "c++"] + srcs + ["-o", tmp]
+           "-I", os.path.join(ROOT, "include"), "-DFDAS_HARM_BATCHED_GRID=3",
+           "-x", "c++"] + srcs + ["-o", tmp]
     subprocess.run(cmd, check=True)
     os.replace(tmp, OUT)
     return OUT

@@ -308,3 +308,51 @@ def test_emulated_candidates_vs_oracle(emu, H):
     assert emu.fdas_find_candidates(_p(S), ctypes.c_int64(N), K, H, ctypes.c_float(thr), None, 0,
                                     _p(count), None) == 0
     assert int(count[0]) == n
+
+
+def test_emulated_batched_harmonic_sums_and_candidates(emu):
+    # ragged spectra (one empty, one single-bin) packed as correlate_batched
+    # lays out its planes; folds chained in one launch each; bitwise equal to
+    # the oracle per spectrum, candidates equal to the per-spectrum peak sets
+    from oracle import harmonic as oh
+    K = 21
+    lens = [300, 0, 1, 97, 130]
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    planes = [syn.random_plane(30 + b, K, n) for b, n in enumerate(lens)]
+    flat = np.concatenate([p.reshape(-1) for p in planes]).astype(np.float32)
+    nspec = len(lens)
+    emu.fdas_harmonic_batched_workspace_bytes.restype = ctypes.c_size_t
+    wsb = emu.fdas_harmonic_batched_workspace_bytes(nspec)
+    ws = np.zeros(wsb // 8 + 1, dtype=np.int64)
+    prev = None
+    c = (K - 1) // 2
+    for H in (2, 4, 8):
+        KH = 2 * (c // H) + 1
+        pre = np.concatenate([[0], np.cumsum([(n + H - 1) // H for n in lens])]).astype(np.int64)
+        buf, S = _guarded((KH * int(pre[-1]),))
+        assert emu.fdas_harmonic_sum_batched(_p(flat), _p(offs), nspec, K, H,
+                                             _p(prev) if prev is not None else None, _p(S),
+                                             _p(ws), ctypes.c_size_t(wsb), None) == 0
+        _check_guards(buf, S)
+        S = S.copy()
+        for b, n in enumerate(lens):
+            got = S[KH * pre[b]:KH * pre[b + 1]].reshape(KH, -1)
+            assert np.array_equal(got, oh.harmonic_sum(planes[b], H)), (H, b)
+        prev = S
+        if H == 4:
+            thr = float(np.quantile(S, 0.9))
+            out = np.zeros(2 * 4096, dtype=np.int64)
+            count = np.zeros(1, dtype=np.uint32)
+            assert emu.fdas_find_candidates_batched(_p(S), _p(offs), nspec, K, H,
+                                                    ctypes.c_float(thr), _p(out), 4096,
+                                                    _p(count), _p(ws), ctypes.c_size_t(wsb),
+                                                    None) == 0
+            rec = out.view(np.dtype([("r", "<i8"), ("row", "<i4"), ("power", "<f4")]))
+            rec = rec[:int(count[0])]
+            got = sorted((int(r), int(row)) for r, row in zip(rec["r"], rec["row"]))
+            want = []
+            row0 = c - (KH - 1) // 2
+            for b in range(nspec):
+                for k, r in oh.peaks(S[KH * pre[b]:KH * pre[b + 1]].reshape(KH, -1), thr):
+                    want.append((int(offs[b] + r), int(row0 + k)))
+            assert got == sorted(want) and len(want) > 0
