@@ -49,6 +49,55 @@ def forward_work(N: int, K: int, M: int, L: int):
     return bytes_, flops
 
 
+def backward_work(N: int, K: int, M: int, L: int, want_taps: bool):
+    """Algorithmic HBM bytes and flops of one adjoint call: read the
+    spectrum (8 B/bin), dL/dP (4 B/point) and the bank, write the spectrum
+    gradient (8 B/bin) and the taps gradient (8 B/tap).  Per window of
+    L - M owned bins: the window's FFT and, per template, the multiply, the
+    inverse FFT that recomputes y, g = 2 w y (2 flop/elem), FFT(g) and the
+    accumulate (8 flop/elem); one inverse FFT of the accumulator per window.
+    The taps gradient adds, per template and window, a conjugate multiply
+    and an inverse FFT."""
+    S = -(-N // (L - M))
+    bytes_ = 8 * N + 4 * K * N + 8 * K * L + 8 * N + (8 * K * M if want_taps else 0)
+    flops = S * 2 * fft_flops(L) + S * K * (2 * fft_flops(L) + 16 * L)
+    if want_taps:
+        flops += S * K * (fft_flops(L) + 6 * L)
+    return bytes_, flops
+
+
+def roof_pair(bytes_, flops, ms):
+    """Achieved HBM and ALU rates of a call against both peaks."""
+    sec = ms / 1e3
+    return {"hbm_GBps": round(bytes_ / sec / 1e9, 2),
+            "hbm_frac": round(bytes_ / sec / 1e9 / HBM_PEAK_GBS, 4),
+            "alu_TFLOPs": round(flops / sec / 1e12, 3),
+            "alu_frac": round(flops / sec / 1e12 / ALU_PEAK_TFLOPS, 4)}
+
+
+def hbm_stream(fdas, torch, nbytes: int, steps: int):
+    """Bandwidth the library's streaming write and read probes reach on
+    this device over an nbytes buffer (GB/s), the practical ceiling beside
+    the published peak."""
+    buf = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    sums = torch.empty(fdas._lib.STREAM_PARTIALS, dtype=torch.float32, device="cuda")
+
+    def wr():
+        fdas.fdas_stream_write(buf, 1.0)
+
+    def rd():
+        fdas.fdas_stream_read(buf, sums)
+
+    wr(); rd()
+    ms_w = _timed(torch, wr, steps)
+    ms_r = _timed(torch, rd, steps)
+    ok = float(sums.double().sum().item()) == float(buf.numel())
+    del buf, sums
+    torch.cuda.empty_cache()
+    return {"bytes": nbytes, "write_GBps": round(nbytes / ms_w / 1e6, 1),
+            "read_GBps": round(nbytes / ms_r / 1e6, 1), "read_sum_checked": ok}
+
+
 def kernel_sources_hash() -> str:
     h = hashlib.sha256()
     for f in ("fdas_kernels.hip", "fdas_fft.hpp"):
@@ -318,6 +367,9 @@ def bench_fwd_bwd(fdas, torch, steps: int):
     pts = K * N
     out = {"workload": f"2^20 bins, {K} templates x {M} taps, segment {L}",
            "points": pts, "segment": L,
+           "backward_roofline": roof_pair(*backward_work(N, K, M, L, True), ms_b),
+           "backward_spec_only_roofline": roof_pair(*backward_work(N, K, M, L, False),
+                                                    per_L[L]["backward_spec_only_ms"]),
            "forward_ms": ms_f, "forward_points_per_s": pts / ms_f * 1e3,
            "backward_ms": ms_b, "backward_spec_only_ms": per_L[L]["backward_spec_only_ms"],
            "fwd_bwd_points_per_s": pts / (ms_f + ms_b) * 1e3,
@@ -388,6 +440,9 @@ def bench_workload5(fdas, torch, steps: int):
            f"forward_batched_ms_segment_{L_spec}": ms_spec, "segment_autotuned": L,
            "forward_batched_ms": ms_f, "forward_points_per_s": pts / ms_f * 1e3,
            "backward_spec_ms": ms_b, "fwd_bwd_points_per_s": pts / (ms_f + ms_b) * 1e3,
+           "backward_spec_roofline": roof_pair(
+               *[sum(x) for x in zip(*(backward_work(int(o[b + 1] - o[b]), K, M, L, False)
+                                       for b in range(nspec)))], ms_b),
            "fwd_bwd_over_fwd_time": (ms_f + ms_b) / ms_f}
     del specs, wts, grads, bws
     torch.cuda.empty_cache()
@@ -649,6 +704,10 @@ def main() -> int:
     # the binding roof is the one the kernel is closer to
     roof, other = (alu, hbm) if alu["frac"] >= hbm["frac"] else (hbm, alu)
 
+    stream_peaks = hbm_stream(fdas, torch, 4 << 30, max(5, args.steps // 2))
+    print(f"# streaming probes: {json.dumps(stream_peaks)}", file=sys.stderr, flush=True)
+    hbm["frac_of_measured_write"] = round(hbm["achieved"] / stream_peaks["write_GBps"], 4)
+
     out = {
         "metric": "f-fdot points/s (templates x bins), fused FDAS forward correlation",
         "value": K * N / sec,
@@ -673,6 +732,7 @@ def main() -> int:
         "segment_selection_ms": {str(k): v for k, v in per_L.items()},
         "algorithmic_bytes_per_launch": bytes_,
         "algorithmic_flops_per_launch": flops,
+        "hbm_stream_measured": stream_peaks,
     }
     del plane
     torch.cuda.empty_cache()

@@ -432,6 +432,24 @@ int fdas_find_candidates_batched(const float *sums_dev, const int64_t *offsets_d
                                  int capacity, unsigned *count_dev, void *ws_dev,
                                  size_t ws_bytes, hipStream_t stream);
 
+/*
+ * Measurement helpers (not part of the method): streaming passes over device
+ * memory that give the bandwidth a plain streaming kernel reaches on the
+ * device, against which the correlation's plane write and the harmonic
+ * gathers are read beside the published peak.
+ *
+ * fdas_stream_write: dst_dev[i] = value for i < n (float, device, 16-byte
+ * aligned), one pass of 16-byte stores.  fdas_stream_read: reads the n
+ * floats of src_dev (16-byte aligned) with non-temporal 16-byte loads and
+ * writes FDAS_STREAM_PARTIALS partial sums to sums_dev (device float, one
+ * per workgroup, summed in an unspecified order; their total is the sum of
+ * the buffer).  n == 0 is valid (the write does nothing, the read writes
+ * zeros).  Asynchronous on `stream`; no allocation.
+ */
+#define FDAS_STREAM_PARTIALS 2048
+int fdas_stream_write(float *dst_dev, int64_t n, float value, hipStream_t stream);
+int fdas_stream_read(const float *src_dev, int64_t n, float *sums_dev, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,7 +21,8 @@ from ._lib import (FdasError, fdas_backward_workspace_bytes, fdas_bank_elems,  #
                    fdas_prepare_bank_sym, fdas_make_templates_half, fdas_correlate_fourier2,
                    fdas_correlate_fourier2_ex, fdas_harmonic_shape, fdas_harmonic_sum,
                    fdas_find_candidates, fdas_harmonic_batched_workspace_bytes,
-                   fdas_harmonic_sum_batched, fdas_find_candidates_batched, lib)
+                   fdas_harmonic_sum_batched, fdas_find_candidates_batched,
+                   fdas_stream_write, fdas_stream_read, lib)
 
 
 def make_bank(zmax: float, dz: float, M: int, L: int, device="cuda"):

@@ -66,7 +66,12 @@ SIGNATURES = [
     ("fdas_harmonic_sum_batched", _I, [_P, _P, _I, _I, _I, _P, _P, _P, _SZ, _P]),
     ("fdas_find_candidates_batched", _I, [_P, _P, _I, _I, _I, ctypes.c_float, _P, _I, _P, _P,
                                           _SZ, _P]),
+    ("fdas_stream_write", _I, [_P, _I64, ctypes.c_float, _P]),
+    ("fdas_stream_read", _I, [_P, _I64, _P, _P]),
 ]
+
+# partial sums written by fdas_stream_read
+STREAM_PARTIALS = 2048
 
 # fdas_candidate: {int64 r; int32 row; float power} (16 bytes)
 CANDIDATE_BYTES = 16
@@ -426,3 +431,22 @@ def fdas_find_candidates_batched(sums, offsets, nspec: int, K: int, H: int, thre
                                               _ptr(out), capacity, _ptr(count), _ptr(ws),
                                               ws.numel(), _stream(stream, sums)),
            "fdas_find_candidates_batched")
+
+
+def fdas_stream_write(dst, value: float, stream=None) -> None:
+    """dst (float32 device tensor, 16-byte aligned) filled with `value` by
+    the streaming write probe."""
+    import torch
+    _require(dst, torch.float32, "dst")
+    _check(lib().fdas_stream_write(_ptr(dst), dst.numel(), value, _stream(stream, dst)),
+           "fdas_stream_write")
+
+
+def fdas_stream_read(src, sums, stream=None) -> None:
+    """Streaming read probe: STREAM_PARTIALS partial sums of src (float32
+    device tensor, 16-byte aligned) into sums."""
+    import torch
+    _require(src, torch.float32, "src")
+    _require(sums, torch.float32, "sums", STREAM_PARTIALS)
+    _check(lib().fdas_stream_read(_ptr(src), src.numel(), _ptr(sums), _stream(stream, src)),
+           "fdas_stream_read")

@@ -22,7 +22,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfdas.so")
 SOURCES = ["fdas_api.cpp", "fdas_templates.cpp", "fdas_tune.cpp", "fdas_kernels.hip",
-           "fdas_r2c.hip", "fdas_harmonic.hip"]
+           "fdas_r2c.hip", "fdas_harmonic.hip", "fdas_stream.hip"]
 
 ARCH = "gfx950"
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-ffp-contract=off",

@@ -805,4 +805,31 @@ int fdas_find_candidates_batched(const float* sums_dev, const int64_t* offsets_d
     return ok();
 }
 
+int fdas_stream_write(float* dst_dev, int64_t n, float value, hipStream_t stream)
+{
+    if (n < 0)
+        return fail(FDAS_INVALID_ARG, "n must be >= 0");
+    if (n == 0)
+        return ok();
+    if (!dst_dev || !aligned(dst_dev, 16))
+        return fail(FDAS_INVALID_ARG, "dst must be a 16-byte aligned device pointer");
+    const hipError_t e = fdas::launch_stream_write(dst_dev, n, value, stream);
+    return e == hipSuccess ? ok() : hip_fail(e, "stream write launch");
+}
+
+int fdas_stream_read(const float* src_dev, int64_t n, float* sums_dev, hipStream_t stream)
+{
+    if (n < 0)
+        return fail(FDAS_INVALID_ARG, "n must be >= 0");
+    if (!sums_dev || !aligned(sums_dev, 4))
+        return fail(FDAS_INVALID_ARG, "sums must be a 4-byte aligned device pointer");
+    if (n > 0 && (!src_dev || !aligned(src_dev, 16)))
+        return fail(FDAS_INVALID_ARG, "src must be a 16-byte aligned device pointer");
+    if (n > 0 && overlaps(sums_dev, FDAS_STREAM_PARTIALS * sizeof(float), src_dev,
+                          (size_t)n * sizeof(float)))
+        return fail(FDAS_INVALID_ARG, "sums must not overlap src");
+    const hipError_t e = fdas::launch_stream_read(n > 0 ? src_dev : nullptr, n, sums_dev, stream);
+    return e == hipSuccess ? ok() : hip_fail(e, "stream read launch");
+}
+
 }  // extern "C"

@@ -72,4 +72,9 @@ hipError_t launch_candidates_batched(const float* sums, const int64_t* offsets, 
                                      unsigned* count, int64_t* colpre, int64_t* prevpre,
                                      hipStream_t s);
 
+// Streaming probes: n floats written with `value`, or read and summed into
+// sums[FDAS_STREAM_PARTIALS] (one partial per workgroup).
+hipError_t launch_stream_write(float* dst, int64_t n, float value, hipStream_t s);
+hipError_t launch_stream_read(const float* src, int64_t n, float* sums, hipStream_t s);
+
 }  // namespace fdas

@@ -14,7 +14,8 @@ CXX = "/opt/rocm/llvm/bin/clang++"
 def build() -> str:
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
     srcs = [os.path.join(CSRC, f) for f in ("fdas_api.cpp", "fdas_templates.cpp", "fdas_kernels.hip",
-                                                  "fdas_r2c.hip", "fdas_harmonic.hip")]
+                                                  "fdas_r2c.hip", "fdas_harmonic.hip",
+                                                  "fdas_stream.hip")]
     tmp = OUT + f".tmp{os.getpid()}"
     # clang (ROCm's, as a host compiler): the kernels use clang vector types
     # a small persistent grid for the batched harmonic kernels: every

@@ -247,3 +247,22 @@ def test_harmonic_validation_before_any_device_call():
                                   None) == _lib.FDAS_INVALID_ARG
     assert L.fdas_find_candidates(None, 1000, 85, 4, 1.0, out, 10, count, None) == \
         _lib.FDAS_INVALID_ARG
+
+
+def test_stream_probe_validation_before_any_device_call():
+    L = _lib.lib()
+    buf, sums = _fake(0x10000000), _fake(0x20000000)
+    assert _lib.STREAM_PARTIALS == 2048
+    assert L.fdas_stream_write(buf, -1, 1.0, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_stream_write(None, 0, 1.0, None) == _lib.FDAS_OK          # nothing to do
+    assert L.fdas_stream_write(None, 16, 1.0, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_stream_write(_fake(0x10000008), 16, 1.0, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_stream_read(buf, -1, sums, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_stream_read(buf, 16, None, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_stream_read(None, 16, sums, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_stream_read(_fake(0x10000004), 16, sums, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_stream_read(buf, 16, _fake(0x20000002), None) == _lib.FDAS_INVALID_ARG
+    # the partial sums inside the buffer being read
+    assert L.fdas_stream_read(buf, 1 << 20, _fake(0x10000000 + 4096), None) == \
+        _lib.FDAS_INVALID_ARG
+

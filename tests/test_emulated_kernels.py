@@ -356,3 +356,22 @@ def test_emulated_batched_harmonic_sums_and_candidates(emu):
                 for k, r in oh.peaks(S[KH * pre[b]:KH * pre[b + 1]].reshape(KH, -1), thr):
                     want.append((int(offs[b] + r), int(row0 + k)))
             assert got == sorted(want) and len(want) > 0
+
+
+@pytest.mark.parametrize("n", [0, 3, 4, 1027, 4096 * 256 + 5])
+def test_stream_probes(emu, n):
+    """The streaming write fills exactly n floats (tails included) and the
+    read's partial sums add up to the buffer's sum, with the partials of
+    workgroups not launched set to zero."""
+    P = 2048
+    buf, arr = _guarded((n,))
+    assert emu.fdas_stream_write(_p(arr) if n else None, ctypes.c_int64(n), ctypes.c_float(1.5),
+                                 None) == 0
+    _check_guards(buf, arr)
+    assert np.all(arr == np.float32(1.5))
+    vals = np.arange(n, dtype=np.float32) % 7      # small integers: every sum is exact
+    sums = np.full(P, np.nan, dtype=np.float32)
+    assert emu.fdas_stream_read(_p(vals) if n else None, ctypes.c_int64(n), _p(sums), None) == 0
+    assert np.all(np.isfinite(sums))
+    assert float(sums.astype(np.float64).sum()) == float(vals.astype(np.float64).sum())
+
