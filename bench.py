@@ -181,9 +181,48 @@ def cpu_baseline(spec_np, zmax, dz, M, K, target_s: float):
             reps = int(reps * grow) + 1
     what = (f"the whole plane ({K} templates x {N} bins) x{reps}" if cols == N else
             f"all {K} templates x bins [0, {cols})")
-    return {"value": K * cols * reps / dt, "unit": "points/s", "cores": native.num_threads(),
+    rate = K * cols * reps / dt
+    return {"value": rate, "unit": "points/s", "cores": native.num_threads(),
             "kind": "oracle", "seconds": round(dt, 3),
-            "sample": f"{what} of the 2^21-bin spectrum, direct FP64 sum over {M} taps"}
+            "sample": f"{what} of the 2^21-bin spectrum, direct FP64 sum over {M} taps",
+            "extrapolated": cpu_extrapolated(rate, M, K, target_s / 4)}
+
+
+def cpu_extrapolated(rate_headline, M_headline, K_headline, target_s: float):
+    """The oracle's time for the two ragged workloads, from samples: the
+    direct sum costs the same per point for every spectrum of a given tap
+    count, so the 256-spectrum batch (same templates as the headline) takes
+    its points over the headline rate, and the large-zmax batch (512 taps)
+    is sampled on a column range of a noise spectrum of its geometry and
+    scaled by its exact point count."""
+    import fdas_synth as syn
+    from oracle import native
+    from oracle import templates as ot
+    out = []
+    n3 = int(syn.ragged_lengths(3).sum())
+    out.append({"workload": f"256 ragged spectra (sum {n3} bins), {K_headline} templates x "
+                            f"{M_headline} taps", "points": K_headline * n3,
+                "oracle_points_per_s": rate_headline,
+                "oracle_seconds": K_headline * n3 / rate_headline,
+                "sample": "the headline sample (same templates and taps)"})
+    T5 = ot.templates(200.0, 2.0, 512)
+    K5 = T5.shape[0]
+    spec = syn.random_spectrum(5, 1 << 21)
+    cols, dt = 512, 0.0
+    while True:
+        t = time.perf_counter()
+        native.power(spec, T5, 0, cols)
+        dt = time.perf_counter() - t
+        if dt >= 0.5 * target_s or cols >= len(spec):
+            break
+        cols = int(min(len(spec), cols * max(2.0, 0.8 * target_s / max(dt, 1e-3))))
+    r5 = K5 * cols / dt
+    n5 = int(syn.ragged_lengths(5).sum())
+    out.append({"workload": f"64 ragged spectra (sum {n5} bins), {K5} templates x 512 taps",
+                "points": K5 * n5, "oracle_points_per_s": r5, "oracle_seconds": K5 * n5 / r5,
+                "sample": f"all {K5} templates x bins [0, {cols}) of a 2^21-bin noise spectrum, "
+                          f"{round(dt, 3)} s"})
+    return out
 
 
 def _events(torch):

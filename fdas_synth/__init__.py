@@ -129,6 +129,21 @@ def _separated(rng, count, lo, hi, min_sep, zlo, zhi, amp):
     return out
 
 
+_RAGGED = {3: (256, 18, 21), 5: (64, 21, 22)}   # count, log2 of the length range
+
+
+def _ragged_lengths(rng, number):
+    count, lo, hi = _RAGGED[number]
+    lens = np.floor(np.exp(rng.uniform(lo * math.log(2), hi * math.log(2), count)))
+    return lens.astype(np.int64)
+
+
+def ragged_lengths(number: int) -> np.ndarray:
+    """The spectrum lengths of ragged workload 3 or 5 (the first draws of its
+    stream), without synthesising the spectra."""
+    return _ragged_lengths(np.random.default_rng(number), number)
+
+
 def workload(number: int, L: int | None = None, nspec: int | None = None,
              length_scale: float = 1.0) -> Workload:
     """Build workload ``number`` (1..5).
@@ -151,11 +166,10 @@ def workload(number: int, L: int | None = None, nspec: int | None = None,
                         "2^21 bins, 85 templates x 256 taps")
     if number in (3, 5):
         if number == 3:
-            count, lo, hi, zr, nsig, zmax, M, Ld = 256, 18, 21, 60.0, 1, 84.0, 256, 2048
+            zr, nsig, zmax, M, Ld = 60.0, 1, 84.0, 256, 2048
         else:
-            count, lo, hi, zr, nsig, zmax, M, Ld = 64, 21, 22, 190.0, 4, 200.0, 512, 8192
-        lens = np.floor(np.exp(rng.uniform(lo * math.log(2), hi * math.log(2), count)))
-        lens = lens.astype(np.int64)
+            zr, nsig, zmax, M, Ld = 190.0, 4, 200.0, 512, 8192
+        lens = _ragged_lengths(rng, number)
         if nspec is not None:
             lens = lens[:nspec]
         if length_scale != 1.0:
