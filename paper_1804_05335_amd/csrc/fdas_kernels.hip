@@ -5,6 +5,7 @@
 
 #include <atomic>
 #include <cstdint>
+#include <type_traits>
 
 #include "fdas_fft.hpp"
 #include "fdas_internal.h"
@@ -127,25 +128,24 @@ struct Fwd {
 
     // Symmetric bank (only the rows z >= 0, template index c = (K-1)/2 on):
     // the row of template zi < c is the mirror of row c - zi, since
-    // T_{-z} = conj T_z gives H_{-z}[p] = conj H_z[(L - p) mod L].
+    // T_{-z} = conj T_z gives H_{-z}[p] = conj H_z[(L - p) mod L].  For lane
+    // t and p = t + T m, (L - p) mod L = (b + T (E-1-m)) mod L with
+    // b = T - t, so the mirrored row is read like a plain one from the lane
+    // base b, in "load order" H[m'] = H_row[(b + T m') mod L] (only lane 0's
+    // last slot wraps, to index 0), and its consumer takes
+    // H_zi[t + T m] = conj(H[E-1-m]): a register renaming and a conjugate
+    // that the multiply absorbs.  Rows zi >= c (row zi - c) load in natural
+    // order.  The choice is uniform, so the load has no branch.
     __device__ static void load_row_sym(float2 (&H)[E], const float2* __restrict__ bank, int zi,
                                         int c, int t)
     {
-        if (zi >= c) {
-            load_row(H, bank, zi - c, t);
-        } else {
-            // position p = t + T m mirrors to (L - p) mod L: L - t - T m for
-            // m >= 1 (in (0, L) for every lane), and (L - t) mod L for m = 0
-            const float2* h = bank + (int64_t)(c - zi) * L;
-            const float2* hr = h + (L - t);
-            const float2 v0 = h[(L - t) & (L - 1)];
-            H[0] = make_float2(v0.x, -v0.y);
+        const bool mir = zi < c;
+        const float2* h = bank + (int64_t)(mir ? c - zi : zi - c) * L;
+        const int b = mir ? T - t : t;
 #pragma unroll
-            for (int m = 1; m < E; ++m) {
-                const float2 v = hr[-T * m];
-                H[m] = make_float2(v.x, -v.y);
-            }
-        }
+        for (int m = 0; m < E - 1; ++m)
+            H[m] = h[b + T * m];
+        H[E - 1] = h[(b + T * (E - 1)) & (L - 1)];
     }
 
     template <bool SYM>
@@ -198,7 +198,11 @@ struct Fwd {
         load_window(X, spec, N, out0 - M / 2, t);
         F::template run<false>(X, la, lb, tw, t);
 
-        for (int z = z0; z < z1; ++z) {
+        static_assert(!(SYM && (IB || DUAL)), "the symmetric bank is for the plain plane");
+        // One template; MIR: H holds a mirrored row in load order (symmetric
+        // bank, z < c), consumed reversed and conjugated.
+        auto one = [&](int z, auto mir_tag) {
+            constexpr bool MIR = decltype(mir_tag)::value;
             float2 v[E];
             const int znext = z + 1 == K ? 0 : z + 1;
             auto next = [&]() { load_bank_row<SYM>(H, bank, znext, K, t); };
@@ -219,9 +223,15 @@ struct Fwd {
                     __builtin_amdgcn_raw_buffer_store_b64(pp, rs, seg_off<8>(t + T * m, M / 2), 0,
                                                           kNonTemporal);
                 }
-                continue;
+                return;
             }
-            if constexpr (!IB) {
+            if constexpr (MIR) {
+                float2 Hr[E];
+#pragma unroll
+                for (int m = 0; m < E; ++m)
+                    Hr[m] = H[E - 1 - m];
+                F::template run_mul_hook<true, kMulConj>(X, Hr, v, la, lb, tw, t, next);
+            } else if constexpr (!IB) {
                 F::template run_mul_hook<true, kMul>(X, H, v, la, lb, tw, t, next);
             } else {
                 // the interbinned epilogue holds more values; the next row is
@@ -285,6 +295,18 @@ struct Fwd {
                 la = lb;
                 lb = tmp;
             }
+        };
+        if constexpr (SYM) {
+            // the mirrored templates first, then the stored rows: each loop
+            // has one multiply form and no per-template branch
+            const int zm = min(max((K - 1) / 2, z0), z1);
+            for (int z = z0; z < zm; ++z)
+                one(z, std::true_type{});
+            for (int z = zm; z < z1; ++z)
+                one(z, std::false_type{});
+        } else {
+            for (int z = z0; z < z1; ++z)
+                one(z, std::false_type{});
         }
     }
 };
