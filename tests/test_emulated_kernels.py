@@ -217,6 +217,14 @@ def test_emulated_symmetric_bank(emu, L, M, N, zmax):
     one = np.zeros((K, N), dtype=np.float32)
     assert emu.fdas_correlate(_p(A), ctypes.c_int64(N), _p(full), K, M, L, _p(one), None) == 0
     assert _rel(plane, one) < TOL
+    # other grids split the (segment, template) items elsewhere, so workgroup
+    # ranges start, end and cross the first stored row (z = 0) at other
+    # templates: the plane is the same bit for bit
+    for grid in (1, 2, 5, 13):
+        again = np.zeros((K, N), dtype=np.float32)
+        assert emu.fdas_correlate_sym_ex(_p(A), ctypes.c_int64(N), _p(sym), K, M, L, _p(again),
+                                         grid, None) == 0
+        assert np.array_equal(again, plane), grid
 
 
 @pytest.mark.parametrize("L,M,N,zmax", [(512, 64, 1500, 10.0), (2048, 256, 3900, 6.0),

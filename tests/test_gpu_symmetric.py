@@ -72,3 +72,20 @@ def test_symmetric_bank_workload2_sampled(fd):
 def test_symmetric_bank_large_zmax_segment_8192(fd):
     w = syn.workload(5, nspec=1)
     _sampled(fd, w.spectra[0], w.zmax, w.dz, w.M, 8192, 5, 40000)
+
+
+@pytest.mark.parametrize("L", [512, 2048])
+def test_symmetric_bank_grid_invariance(fd, L):
+    """Persistent grids of other sizes split the (segment, template) items
+    elsewhere: workgroup ranges start, end and cross the first stored row
+    (z = 0) at other templates, and the plane is the same bit for bit."""
+    w = syn.workload(1)
+    taps, _ = fd.make_bank(w.zmax, w.dz, w.M, L)
+    K = taps.shape[0]
+    sym = fd.prepare_bank_sym(taps, L)
+    spec = torch.from_numpy(w.spectra[0]).cuda()
+    ref = fd.correlate_sym(spec, sym, K, w.M, L).cpu()
+    for grid in (1, 3, 7, 64, 1000):
+        got = fd.correlate_sym(spec, sym, K, w.M, L, grid=grid).cpu()
+        assert torch.equal(got, ref), grid
+
