@@ -31,6 +31,21 @@ HBM_PEAK_GBS = 8000.0                      # MI355X HBM3E, GB/s
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 
 
+# LDS: 64 banks x 4 B per clock per CU (the bank structure the kernels' LDS
+# layout is built for), 256 CUs, 2.4 GHz
+LDS_PEAK_GBS = 256 * 64 * 4 * 2.4e9 / 1e9
+
+
+def forward_lds_bytes(N: int, K: int, M: int, L: int) -> int:
+    """LDS bytes one forward launch moves: every transform of a segment (the
+    window's and one inverse per template) exchanges its L complex values
+    through LDS twice (write + read, 8 B each) at L = 2048 and 4096 (three
+    radix passes); at other L the pass count differs and this is a lower
+    bound."""
+    S = -(-N // (L - M))
+    return S * (K + 1) * 2 * 2 * L * 8
+
+
 def fft_flops(L: int) -> float:
     """Radix-4 flop estimate of one length-L complex FFT."""
     return 4.25 * L * math.log2(L)
@@ -737,6 +752,10 @@ def main() -> int:
     alu = {"bound": "alu", "achieved": round(flops / ksec / 1e12, 3), "peak": round(ALU_PEAK_TFLOPS, 2),
            "unit": "TFLOP/s"}
     alu["frac"] = round(alu["achieved"] / alu["peak"], 4)
+    lds_b = forward_lds_bytes(N, K, M, L)
+    lds = {"bound": "lds", "achieved": round(lds_b / ksec / 1e9, 1), "peak": round(LDS_PEAK_GBS, 1),
+           "unit": "GB/s", "bytes_per_launch": lds_b}
+    lds["frac"] = round(lds["achieved"] / lds["peak"], 4)
     traffic = read_traffic(f"forward_L{L}_2e21x85_counters.md")
     for r in (hbm, alu):
         r["traffic"] = traffic
@@ -766,6 +785,7 @@ def main() -> int:
                    "grid": args.grid or "resident"},
         "roofline": roof,
         "roofline_other": other,
+        "roofline_lds": lds,
         "kernel_ms": ms_k,
         "host_enqueue_ms": ms_host,
         "segment_selection_ms": {str(k): v for k, v in per_L.items()},
