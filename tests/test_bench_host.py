@@ -30,6 +30,25 @@ def test_forward_work_model_at_the_headline_size():
     assert flops == S * fft + S * K * (6 * L + fft) + 3 * K * N
 
 
+def test_lds_and_adjoint_work_models():
+    N, K, M, L = 1 << 21, 85, 256, 2048
+    # two exchanges of L complex values (write + read) per transform, K + 1
+    # transforms per segment: about 6.6 GB per launch at the headline size
+    assert bench.forward_lds_bytes(N, K, M, L) == 1171 * 86 * 4 * L * 8
+    # adjoint at 2^20 bins, 85 x 128 taps, L = 512: windows of L - M owned bins
+    N, K, M, L = 1 << 20, 85, 128, 512
+    S = -(-N // (L - M))
+    fft = 4.25 * L * 9
+    b_spec, f_spec = bench.backward_work(N, K, M, L, False)
+    b_full, f_full = bench.backward_work(N, K, M, L, True)
+    assert b_spec == 8 * N + 4 * K * N + 8 * K * L + 8 * N
+    assert b_full == b_spec + 8 * K * M
+    assert f_spec == S * 2 * fft + S * K * (2 * fft + 16 * L)
+    assert f_full == f_spec + S * K * (fft + 6 * L)
+    r = bench.roof_pair(b_full, f_full, 1.0)
+    assert abs(r["hbm_GBps"] - b_full / 1e6) < 0.01 and 0 < r["alu_frac"] < 1
+
+
 def _summary(path, khash, fetch, write):
     with open(path, "w") as f:
         f.write("# summary\n\n| counter | value |\n|---|---|\n| FETCH_SIZE | 1 KiB |\n\n")
