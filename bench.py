@@ -46,6 +46,24 @@ def forward_lds_bytes(N: int, K: int, M: int, L: int) -> int:
     return S * (K + 1) * 2 * 2 * L * 8
 
 
+# Real-time series counts of the paper's custom-FFT FDAS on a P100 for
+# time series of 2^21 samples, without interbinning (Sec. 6, Table 4),
+# keyed by the number of templates: context measured on other hardware.
+PAPER_P100_SERIES_2E21 = {64: 41645, 96: 26801, 128: 20147, 192: 12216, 256: 8338}
+
+
+def paper_units(points_per_s: float, K: int) -> dict:
+    """The rate in the paper's unit: how many time series, sampled every
+    64 us, one GPU correlates within their own observation time.  A series
+    of n samples gives n/2 bins, so it needs K n/2 plane points per n x 64 us
+    of data: count = points/s x 128 us / K."""
+    return {"real_time_series": round(points_per_s * 128e-6 / K),
+            "definition": "series sampled every 64 us correlated within their observation "
+                          "time: points/s x 128 us / K",
+            "paper_P100_no_interbinning_n_2e21": {str(k): v for k, v in
+                                                 PAPER_P100_SERIES_2E21.items()}}
+
+
 def fft_flops(L: int) -> float:
     """Radix-4 flop estimate of one length-L complex FFT."""
     return 4.25 * L * math.log2(L)
@@ -792,6 +810,7 @@ def main() -> int:
         "algorithmic_bytes_per_launch": bytes_,
         "algorithmic_flops_per_launch": flops,
         "hbm_stream_measured": stream_peaks,
+        "paper_units": paper_units(K * N / sec, K),
     }
     del plane
     torch.cuda.empty_cache()

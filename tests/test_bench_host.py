@@ -49,6 +49,14 @@ def test_lds_and_adjoint_work_models():
     assert abs(r["hbm_GBps"] - b_full / 1e6) < 0.01 and 0 < r["alu_frac"] < 1
 
 
+def test_paper_units():
+    # points/s x 128 us / K: 7e11 points/s at 85 templates is about 1.05e6 series
+    u = bench.paper_units(7e11, 85)
+    assert u["real_time_series"] == round(7e11 * 128e-6 / 85)
+    # the paper's own counts convert back to its derived 2e10 points/s at K = 64
+    assert abs(bench.PAPER_P100_SERIES_2E21[64] * 64 / 128e-6 - 2.08e10) < 0.01e10
+
+
 def _summary(path, khash, fetch, write):
     with open(path, "w") as f:
         f.write("# summary\n\n| counter | value |\n|---|---|\n| FETCH_SIZE | 1 KiB |\n\n")
