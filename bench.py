@@ -624,6 +624,34 @@ def bench_r2c(fdas, torch, steps: int):
         del x, spec, ws
     torch.cuda.empty_cache()
     out["paper_cpu_r2c_ms"] = {"2^21": 30, "2^22": 75, "2^23": 220}
+    # 64 series of 2^22 samples (equal-length dedispersion trials): one
+    # launch per pass for the batch against a loop of single-series calls
+    n, S = 1 << 22, 64
+    x = torch.from_numpy(syn.time_series(22, n)).cuda().repeat(S)
+    spec = torch.empty(S * (n // 2 + 1), dtype=torch.complex64, device="cuda")
+    ws = torch.empty(fdas.fdas_r2c_batched_workspace_bytes(n, S), dtype=torch.uint8,
+                     device="cuda")
+    w1 = fdas.fdas_r2c_workspace_bytes(n)
+
+    def batched():
+        fdas.fdas_r2c_batched(x, n, S, 1.0, spec, ws)
+
+    def loop():
+        for b in range(S):
+            fdas.fdas_r2c(x[b * n:(b + 1) * n], n, 1.0, spec[b * (n // 2 + 1):(b + 1) * (n // 2 + 1)],
+                          ws[:w1])
+
+    batched()
+    loop()
+    ms_b = _timed(torch, batched, max(steps // 2, 3))
+    ms_l = _timed(torch, loop, max(steps // 2, 3))
+    alg = S * (4 * n + 8 * (n // 2 + 1))
+    out["batched_64x2^22"] = {"batched_ms": ms_b, "loop_ms": ms_l,
+                              "speedup_batched_vs_loop": ms_l / ms_b,
+                              "algorithmic_GB_per_s": alg / ms_b / 1e6,
+                              "hbm_frac": alg / ms_b / 1e6 / HBM_PEAK_GBS}
+    del x, spec, ws
+    torch.cuda.empty_cache()
     return out
 
 

@@ -347,6 +347,21 @@ size_t fdas_r2c_workspace_bytes(int64_t n);
 int fdas_r2c(const float *x_dev, int64_t n, float scale, fdas_cf32 *spec_dev, void *ws_dev,
              size_t ws_bytes, hipStream_t stream);
 
+/*
+ * The same for nseries equal-length time series in one launch per pass (the
+ * independent series of a search, e.g. dedispersion trials, whose count
+ * processed in real time the paper reports, Sec. 6).  Series b is x_dev[b n .. (b+1) n) and its
+ * n/2 + 1 bins go to spec_dev[b (n/2 + 1) ..], so spec_dev holds
+ * nseries (n/2 + 1) values; with offsets b (n/2 + 1), b = 0 .. nseries, it
+ * is a packed batch for fdas_correlate_batched whose spectra have n/2 + 1
+ * bins (the Nyquist bin included).  ws_dev: fdas_r2c_batched_workspace_bytes(n,
+ * nseries) bytes, 256-byte aligned.  Each series' bins are bitwise those of
+ * fdas_r2c.  nseries in [1, 65535]; errors and alignment as fdas_r2c.
+ */
+size_t fdas_r2c_batched_workspace_bytes(int64_t n, int nseries);
+int fdas_r2c_batched(const float *x_dev, int64_t n, int nseries, float scale,
+                     fdas_cf32 *spec_dev, void *ws_dev, size_t ws_bytes, hipStream_t stream);
+
 /* ---- harmonic summing and peak candidates ---------------------------------- */
 
 /*

@@ -22,7 +22,8 @@ from ._lib import (FdasError, fdas_backward_workspace_bytes, fdas_bank_elems,  #
                    fdas_correlate_fourier2_ex, fdas_harmonic_shape, fdas_harmonic_sum,
                    fdas_find_candidates, fdas_harmonic_batched_workspace_bytes,
                    fdas_harmonic_sum_batched, fdas_find_candidates_batched,
-                   fdas_stream_write, fdas_stream_read, lib)
+                   fdas_stream_write, fdas_stream_read, fdas_r2c_batched,
+                   fdas_r2c_batched_workspace_bytes, lib)
 
 
 def make_bank(zmax: float, dz: float, M: int, L: int, device="cuda"):
@@ -111,6 +112,21 @@ def spectrum_from_series(x, scale: float = 1.0, spec=None, ws=None):
     if ws is None:
         ws = torch.empty(max(fdas_r2c_workspace_bytes(n), 1), dtype=torch.uint8, device=x.device)
     fdas_r2c(x, n, scale, spec, ws)
+    return spec
+
+
+def spectra_from_series(x, scale: float = 1.0):
+    """Real-to-complex transform of nseries equal-length float32 device time
+    series (a [nseries][n] tensor) in one launch per pass: a [nseries][n/2 + 1]
+    complex64 tensor, each row bitwise the spectrum_from_series of its
+    series.  With offsets b (n/2 + 1), b = 0 .. nseries, its flat view is a
+    packed batch for correlate_batched (spectra of n/2 + 1 bins)."""
+    import torch
+    nseries, n = x.shape
+    spec = torch.empty((nseries, n // 2 + 1), dtype=torch.complex64, device=x.device)
+    ws = torch.empty(max(fdas_r2c_batched_workspace_bytes(n, nseries), 1), dtype=torch.uint8,
+                     device=x.device)
+    fdas_r2c_batched(x.contiguous().view(-1), n, nseries, scale, spec.view(-1), ws)
     return spec
 
 

@@ -66,6 +66,8 @@ SIGNATURES = [
     ("fdas_harmonic_sum_batched", _I, [_P, _P, _I, _I, _I, _P, _P, _P, _SZ, _P]),
     ("fdas_find_candidates_batched", _I, [_P, _P, _I, _I, _I, ctypes.c_float, _P, _I, _P, _P,
                                           _SZ, _P]),
+    ("fdas_r2c_batched_workspace_bytes", _SZ, [_I64, _I]),
+    ("fdas_r2c_batched", _I, [_P, _I64, _I, ctypes.c_float, _P, _P, _SZ, _P]),
     ("fdas_stream_write", _I, [_P, _I64, ctypes.c_float, _P]),
     ("fdas_stream_read", _I, [_P, _I64, _P, _P]),
 ]
@@ -306,6 +308,19 @@ def fdas_r2c(x, n: int, scale: float, spec, ws, stream=None) -> None:
     _require(ws, torch.uint8, "ws", fdas_r2c_workspace_bytes(n))
     _check(lib().fdas_r2c(_ptr(x), n, scale, _ptr(spec), _ptr(ws), ws.numel(),
                           _stream(stream, x)), "fdas_r2c")
+
+
+def fdas_r2c_batched_workspace_bytes(n: int, nseries: int) -> int:
+    return int(lib().fdas_r2c_batched_workspace_bytes(n, nseries))
+
+
+def fdas_r2c_batched(x, n: int, nseries: int, scale: float, spec, ws, stream=None) -> None:
+    import torch
+    _require(x, torch.float32, "x", nseries * n)
+    _require(spec, torch.complex64, "spec", nseries * (n // 2 + 1))
+    _require(ws, torch.uint8, "ws", fdas_r2c_batched_workspace_bytes(n, nseries))
+    _check(lib().fdas_r2c_batched(_ptr(x), n, nseries, scale, _ptr(spec), _ptr(ws), ws.numel(),
+                                  _stream(stream, x)), "fdas_r2c_batched")
 
 
 def fdas_bank_sym_elems(K: int, L: int) -> int:

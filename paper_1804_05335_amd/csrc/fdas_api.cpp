@@ -38,6 +38,13 @@ int hip_fail(hipError_t e, const char* where)
 
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
+// [a, a + na) and [b, b + nb) share a byte (NULL pointers never overlap)
+bool overlaps(const void* a, size_t na, const void* b, size_t nb)
+{
+    const auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+    return a && b && pa < pb + nb && pb < pa + na;
+}
+
 bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
 constexpr int kMaxK = 4096;
@@ -622,6 +629,44 @@ int fdas_r2c(const float* x_dev, int64_t n, float scale, fdas_cf32* spec_dev, vo
     return ok();
 }
 
+size_t fdas_r2c_batched_workspace_bytes(int64_t n, int nseries)
+{
+    const int l = r2c_log2n(n);
+    if (l < 0 || nseries < 1 || nseries > 65535)
+        return 0;
+    return (size_t)nseries * (size_t)(n / 2) * sizeof(fdas_cf32);
+}
+
+int fdas_r2c_batched(const float* x_dev, int64_t n, int nseries, float scale,
+                     fdas_cf32* spec_dev, void* ws_dev, size_t ws_bytes, hipStream_t stream)
+{
+    const int l = r2c_log2n(n);
+    if (l < 0)
+        return fail(FDAS_UNSUPPORTED, "n = %lld is not a power of two in [2^13, 2^27]",
+                    (long long)n);
+    if (nseries < 1 || nseries > 65535)
+        return fail(FDAS_INVALID_ARG, "nseries = %d outside [1, 65535]", nseries);
+    if (!x_dev || !spec_dev || !ws_dev)
+        return fail(FDAS_INVALID_ARG, "x, spec and ws must not be NULL");
+    if (!aligned(x_dev, 8) || !aligned(spec_dev, 8) || !aligned(ws_dev, 256))
+        return fail(FDAS_INVALID_ARG, "misaligned pointer (x and spec 8 B, ws 256 B)");
+    const size_t need = fdas_r2c_batched_workspace_bytes(n, nseries);
+    if (ws_bytes < need)
+        return fail(FDAS_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", ws_bytes,
+                    need);
+    const size_t xbytes = (size_t)nseries * (size_t)n * 4;
+    const size_t sbytes = (size_t)nseries * (size_t)(n / 2 + 1) * 8;
+    if (overlaps(x_dev, xbytes, spec_dev, sbytes) || overlaps(x_dev, xbytes, ws_dev, need) ||
+        overlaps(spec_dev, sbytes, ws_dev, need))
+        return fail(FDAS_INVALID_ARG, "x, spec and ws must not overlap");
+    hipError_t e = fdas::launch_r2c_batched(x_dev, l, nseries, scale,
+                                            reinterpret_cast<float2*>(spec_dev),
+                                            reinterpret_cast<float2*>(ws_dev), stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "batched r2c launch");
+    return ok();
+}
+
 }  // extern "C"
 
 // ---- harmonic summing and peak candidates ---------------------------------------
@@ -637,12 +682,6 @@ int check_harmonic(int64_t N, int K, int H)
     if (!is_pow2(H) || H > 64)
         return fail(FDAS_INVALID_ARG, "H = %d must be a power of two in [1, 64]", H);
     return FDAS_OK;
-}
-
-bool overlaps(const void* a, size_t na, const void* b, size_t nb)
-{
-    const auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
-    return a && b && pa < pb + nb && pb < pa + na;
 }
 
 }  // namespace

@@ -54,6 +54,10 @@ hipError_t launch_backward(const float2* spec, int64_t N, const float2* bank, in
 int r2c_plan(int log2N, int bits[4]);
 hipError_t launch_r2c(const float* x, int log2n, float scale, float2* spec, float2* ws,
                       hipStream_t s);
+// nseries equal-length series one after another: x at stride n floats, ws at
+// stride N and spec at stride N + 1 complex values; one launch per pass.
+hipError_t launch_r2c_batched(const float* x, int log2n, int nseries, float scale, float2* spec,
+                              float2* ws, hipStream_t s);
 
 // Harmonic sums and candidates (fdas_harmonic.hip).
 void harmonic_shape(int64_t N, int K, int H, int* KH, int64_t* NH);

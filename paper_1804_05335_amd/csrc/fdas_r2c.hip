@@ -121,8 +121,12 @@ __device__ __forceinline__ void tile_stages(float2 (&x)[16], int g, int i2, floa
 // and writing `out`.
 template <int RB, bool FIRST>
 __global__ __launch_bounds__(kR2cThreads) void r2c_pass_kernel(
-    const float2* __restrict__ in, float2* __restrict__ out, int log2N, int log2NS)
+    const float2* __restrict__ in, float2* __restrict__ out, int log2N, int log2NS,
+    int64_t in_stride, int64_t out_stride)
 {
+    // series blockIdx.y of a batch (stride 0 and one series otherwise)
+    in += (int64_t)blockIdx.y * in_stride;
+    out += (int64_t)blockIdx.y * out_stride;
     using S = Shape<RB>;
     constexpr int R = S::R, G = S::G, PITCH = S::PITCH, KPL = S::KPL;
     __shared__ float2 tile[G * PITCH];
@@ -194,8 +198,11 @@ __global__ __launch_bounds__(kR2cThreads) void r2c_pass_kernel(
 // W_n^c W_{2R}^k since W_n^NS = W_{2R}.  Needs NS >= 2G (N >= 2^13).
 template <int RB>
 __global__ __launch_bounds__(2 * kR2cThreads, 4) void r2c_last_split_kernel(
-    const float2* __restrict__ in, float2* __restrict__ A, int log2N, int log2n, float scale)
+    const float2* __restrict__ in, float2* __restrict__ A, int log2N, int log2n, float scale,
+    int64_t in_stride, int64_t out_stride)
 {
+    in += (int64_t)blockIdx.y * in_stride;
+    A += (int64_t)blockIdx.y * out_stride;
     using S = Shape<RB>;
     constexpr int R = S::R, G = S::G, PITCH = S::PITCH, KPL = S::KPL;
     constexpr int kTile = G * PITCH;
@@ -278,8 +285,10 @@ __global__ __launch_bounds__(2 * kR2cThreads, 4) void r2c_last_split_kernel(
 // Separate split for N < 2^13: A[k] and A[N-k] from Z[k] and Z[N-k],
 // k in [0, N/2]; Z[N] = Z[0].
 __global__ void r2c_split_kernel(const float2* __restrict__ Z, int64_t N, int log2n, float scale,
-                                 float2* __restrict__ A)
+                                 float2* __restrict__ A, int64_t in_stride, int64_t out_stride)
 {
+    Z += (int64_t)blockIdx.y * in_stride;
+    A += (int64_t)blockIdx.y * out_stride;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k > N / 2)
         return;
@@ -301,25 +310,26 @@ __global__ void r2c_split_kernel(const float2* __restrict__ Z, int64_t N, int lo
 
 template <int RB>
 hipError_t pass_L(const float2* in, float2* out, int log2N, int log2NS, bool first,
-                  hipStream_t s)
+                  int64_t sin, int64_t sout, unsigned nser, hipStream_t s)
 {
-    const unsigned blocks = (unsigned)(((int64_t)1 << log2N) / kR2cTile);
+    const dim3 blocks((unsigned)(((int64_t)1 << log2N) / kR2cTile), nser);
     if (first)
-        hipLaunchKernelGGL((r2c_pass_kernel<RB, true>), dim3(blocks), dim3(kR2cThreads), 0, s,
-                           in, out, log2N, log2NS);
+        hipLaunchKernelGGL((r2c_pass_kernel<RB, true>), blocks, dim3(kR2cThreads), 0, s, in, out,
+                           log2N, log2NS, sin, sout);
     else
-        hipLaunchKernelGGL((r2c_pass_kernel<RB, false>), dim3(blocks), dim3(kR2cThreads), 0, s,
-                           in, out, log2N, log2NS);
+        hipLaunchKernelGGL((r2c_pass_kernel<RB, false>), blocks, dim3(kR2cThreads), 0, s, in, out,
+                           log2N, log2NS, sin, sout);
     return hipGetLastError();
 }
 
 template <int RB>
-hipError_t last_L(const float2* in, float2* A, int log2N, int log2n, float scale, hipStream_t s)
+hipError_t last_L(const float2* in, float2* A, int log2N, int log2n, float scale, int64_t sin,
+                  int64_t sout, unsigned nser, hipStream_t s)
 {
-    // NS / (2G) workgroups of 512 lanes
-    const unsigned blocks = (unsigned)(((int64_t)1 << log2N) / (2 * kR2cTile));
-    hipLaunchKernelGGL((r2c_last_split_kernel<RB>), dim3(blocks), dim3(2 * kR2cThreads), 0, s, in,
-                       A, log2N, log2n, scale);
+    // NS / (2G) workgroups of 512 lanes per series
+    const dim3 blocks((unsigned)(((int64_t)1 << log2N) / (2 * kR2cTile)), nser);
+    hipLaunchKernelGGL((r2c_last_split_kernel<RB>), blocks, dim3(2 * kR2cThreads), 0, s, in, A,
+                       log2N, log2n, scale, sin, sout);
     return hipGetLastError();
 }
 
@@ -347,15 +357,21 @@ int r2c_plan(int log2N, int bits[4])
     return P;
 }
 
-hipError_t launch_r2c(const float* x, int log2n, float scale, float2* spec, float2* ws,
-                      hipStream_t s)
+hipError_t launch_r2c_batched(const float* x, int log2n, int nseries, float scale, float2* spec,
+                              float2* ws, hipStream_t s)
 {
     const int log2N = log2n - 1;
     const int64_t N = (int64_t)1 << log2N;
     int bits[4];
     const int P = r2c_plan(log2N, bits);
-    if (P < 1)
+    if (P < 1 || nseries < 1 || nseries > 65535)
         return hipErrorInvalidValue;
+    const unsigned nser = (unsigned)nseries;
+    // per-series strides (complex values); with one series they are unused
+    const int64_t sx = N, sws = N, ssp = N + 1;
+    auto stride_of = [&](const void* p) {
+        return p == (const void*)x ? sx : (p == (const void*)ws ? sws : ssp);
+    };
     // From N = 2^13 on (NS >= 2G in the last pass) the last pass carries the
     // split and writes spec; the passes before it alternate so that the one
     // before the last writes ws.  Below, every pass alternates so that the
@@ -366,12 +382,13 @@ hipError_t launch_r2c(const float* x, int log2n, float scale, float2* spec, floa
     int log2NS = 0;
     for (int p = 0; p < plain; ++p) {
         float2* dst = ((plain - 1 - p) % 2 == 0) ? ws : spec;
+        const int64_t si = stride_of(src), so = stride_of(dst);
         hipError_t e;
         switch (bits[p]) {
-        case 8: e = pass_L<16>(src, dst, log2N, log2NS, p == 0, s); break;
-        case 7: e = pass_L<8>(src, dst, log2N, log2NS, p == 0, s); break;
-        case 6: e = pass_L<4>(src, dst, log2N, log2NS, p == 0, s); break;
-        case 5: e = pass_L<2>(src, dst, log2N, log2NS, p == 0, s); break;
+        case 8: e = pass_L<16>(src, dst, log2N, log2NS, p == 0, si, so, nser, s); break;
+        case 7: e = pass_L<8>(src, dst, log2N, log2NS, p == 0, si, so, nser, s); break;
+        case 6: e = pass_L<4>(src, dst, log2N, log2NS, p == 0, si, so, nser, s); break;
+        case 5: e = pass_L<2>(src, dst, log2N, log2NS, p == 0, si, so, nser, s); break;
         default: return hipErrorInvalidValue;
         }
         if (e != hipSuccess)
@@ -379,20 +396,27 @@ hipError_t launch_r2c(const float* x, int log2n, float scale, float2* spec, floa
         src = dst;
         log2NS += bits[p];
     }
+    const int64_t si = stride_of(src);
     if (fused) {
         switch (bits[P - 1]) {
-        case 8: return last_L<16>(src, spec, log2N, log2n, scale, s);
-        case 7: return last_L<8>(src, spec, log2N, log2n, scale, s);
-        case 6: return last_L<4>(src, spec, log2N, log2n, scale, s);
-        case 5: return last_L<2>(src, spec, log2N, log2n, scale, s);
+        case 8: return last_L<16>(src, spec, log2N, log2n, scale, si, ssp, nser, s);
+        case 7: return last_L<8>(src, spec, log2N, log2n, scale, si, ssp, nser, s);
+        case 6: return last_L<4>(src, spec, log2N, log2n, scale, si, ssp, nser, s);
+        case 5: return last_L<2>(src, spec, log2N, log2n, scale, si, ssp, nser, s);
         default: return hipErrorInvalidValue;
         }
     }
     const int bs = 256;
     const int64_t nthreads = N / 2 + 1;
-    hipLaunchKernelGGL(r2c_split_kernel, dim3((unsigned)((nthreads + bs - 1) / bs)), dim3(bs), 0,
-                       s, ws, N, log2n, scale, spec);
+    hipLaunchKernelGGL(r2c_split_kernel, dim3((unsigned)((nthreads + bs - 1) / bs), nser), dim3(bs),
+                       0, s, ws, N, log2n, scale, spec, sws, ssp);
     return hipGetLastError();
+}
+
+hipError_t launch_r2c(const float* x, int log2n, float scale, float2* spec, float2* ws,
+                      hipStream_t s)
+{
+    return launch_r2c_batched(x, log2n, 1, scale, spec, ws, s);
 }
 
 }  // namespace fdas

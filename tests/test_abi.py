@@ -183,6 +183,30 @@ def test_r2c_validation_before_any_device_call():
         _lib.FDAS_INVALID_ARG
 
 
+def test_r2c_batched_validation_before_any_device_call():
+    L = _lib.lib()
+    n, S = 1 << 20, 3
+    wsb = L.fdas_r2c_batched_workspace_bytes(n, S)
+    assert wsb == S * (n // 2) * 8
+    assert L.fdas_r2c_batched_workspace_bytes(n, 0) == 0
+    assert L.fdas_r2c_batched_workspace_bytes(n, 65536) == 0
+    assert L.fdas_r2c_batched_workspace_bytes(3 << 18, 1) == 0
+    x, spec, ws = _fake(0x10000000), _fake(0x40000000), _fake(0x80000000)
+    assert L.fdas_r2c_batched(x, 3 << 18, S, 1.0, spec, ws, wsb, None) == _lib.FDAS_UNSUPPORTED
+    for bad in (0, -1, 65536):
+        assert L.fdas_r2c_batched(x, n, bad, 1.0, spec, ws, wsb, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_r2c_batched(x, n, S, 1.0, spec, ws, wsb - 1, None) == \
+        _lib.FDAS_WORKSPACE_TOO_SMALL
+    assert L.fdas_r2c_batched(None, n, S, 1.0, spec, ws, wsb, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_r2c_batched(x, n, S, 1.0, spec, _fake(0x80000080), wsb, None) == \
+        _lib.FDAS_INVALID_ARG
+    # the third series' samples reach into spec, spec's last series into ws
+    assert L.fdas_r2c_batched(x, n, S, 1.0, _fake(0x10000000 + 4 * n * 2 + 8), ws, wsb,
+                              None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_r2c_batched(x, n, S, 1.0, spec, _fake(0x40000000 + 8 * (n // 2 + 1) * 2 + 256),
+                              wsb, None) == _lib.FDAS_INVALID_ARG
+
+
 def test_symmetric_bank_validation():
     L = _lib.lib()
     assert L.fdas_bank_sym_elems(85, 2048) == 44 * 2048

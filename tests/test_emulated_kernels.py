@@ -193,6 +193,33 @@ def test_emulated_r2c_vs_oracle(emu, log2n):
     assert np.linalg.norm(got - ref) < 1e-6 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("log2n", [13, 14, 17])
+def test_emulated_r2c_batched_equals_single(emu, log2n):
+    # three series in one launch per pass (the separate split at 2^13, the
+    # fused last pass above): each series' bins bitwise those of fdas_r2c,
+    # nothing written outside the batch's spectra
+    n, S = 1 << log2n, 3
+    xs = np.stack([syn.time_series(100 * log2n + b, n, [(0.5, 0.1 * b, n / 5 + b, 3.0 * b)])
+                   for b in range(S)])
+    emu.fdas_r2c_batched_workspace_bytes.restype = ctypes.c_size_t
+    emu.fdas_r2c_workspace_bytes.restype = ctypes.c_size_t
+    wsb = emu.fdas_r2c_batched_workspace_bytes(ctypes.c_int64(n), S)
+    assert wsb == S * (n // 2) * 8
+    ws = np.zeros(wsb + 256, dtype=np.uint8)
+    wsp = ctypes.c_void_p((ws.ctypes.data + 255) & ~255)
+    buf, spec = _guarded((S, n + 2))
+    assert emu.fdas_r2c_batched(_p(xs), ctypes.c_int64(n), S, ctypes.c_float(0.5), _p(spec), wsp,
+                                ctypes.c_size_t(wsb), None) == 0
+    _check_guards(buf, spec)
+    w1 = emu.fdas_r2c_workspace_bytes(ctypes.c_int64(n))
+    for b in range(S):
+        one = np.zeros(n + 2, dtype=np.float32)
+        x = np.ascontiguousarray(xs[b])
+        assert emu.fdas_r2c(_p(x), ctypes.c_int64(n), ctypes.c_float(0.5), _p(one), wsp,
+                            ctypes.c_size_t(w1), None) == 0
+        assert np.array_equal(one, spec[b]), b
+
+
 @pytest.mark.parametrize("L,M,N,zmax", [(512, 64, 1500, 10.0), (2048, 256, 3900, 6.0),
                                         (256, 2, 300, 0.0)])
 def test_emulated_symmetric_bank(emu, L, M, N, zmax):

@@ -112,3 +112,55 @@ def test_series_to_plane_end_to_end(fd):
     # the signal is found at its frequency and frequency derivative
     zz, rr = np.unravel_index(int(torch.argmax(plane).item()), plane.shape)
     assert abs(ot.z_grid(zmax, dz)[zz] - z0) <= dz and abs(rr - r0) <= 1.0
+
+
+@pytest.mark.parametrize("log2n,nseries", [(13, 5), (16, 64), (22, 3), (24, 2)])
+def test_r2c_batched_bitwise_equals_single(fd, log2n, nseries):
+    """Equal-length series in one launch per pass: every series' bins are
+    bitwise those of the single-series call (the separate split at 2^13, the
+    fused last pass above it), and nothing is written past the batch."""
+    n = 1 << log2n
+    xs = np.stack([syn.time_series(1000 * log2n + b, n, [(0.3, 0.7 * b, n / 9 + 0.3 * b, 2.0 * b)])
+                   for b in range(nseries)])
+    xd = torch.from_numpy(xs).cuda()
+    guard = 64
+    buf = torch.full((nseries * (n // 2 + 1) + guard,), complex(-3.0, 5.0), dtype=torch.complex64,
+                     device="cuda")
+    spec = buf[:nseries * (n // 2 + 1)]
+    ws = torch.empty(fd.fdas_r2c_batched_workspace_bytes(n, nseries), dtype=torch.uint8,
+                     device="cuda")
+    scale = 1.0 / np.sqrt(n)
+    fd.fdas_r2c_batched(xd.view(-1), n, nseries, scale, spec, ws)
+    torch.cuda.synchronize()
+    assert torch.all(buf[-guard:] == complex(-3.0, 5.0))
+    got = spec.view(nseries, n // 2 + 1)
+    for b in range(nseries):
+        one = fd.spectrum_from_series(xd[b].contiguous(), scale)
+        torch.cuda.synchronize()
+        assert torch.equal(got[b], one), b
+    # one series against the oracle as well
+    ref = r2c.spectrum(xs[-1], scale)
+    assert np.max(np.abs(got[-1].cpu().numpy() - ref)) < TOL * np.max(np.abs(ref))
+
+
+def test_batched_series_to_planes(fd):
+    """Many equal-length series -> spectra (one launch per pass) -> planes of
+    all of them (one launch), the spectra packed with offsets b (n/2 + 1):
+    each plane bitwise the single-series path's."""
+    n, nseries = 1 << 16, 6
+    xs = np.stack([syn.time_series(50 + b, n, [(0.2, 0.0, 7000.4 + 300 * b, 4.0 * b - 10)])
+                   for b in range(nseries)])
+    xd = torch.from_numpy(xs).cuda()
+    scale = 1.0 / np.sqrt(n)
+    specs = fd.spectra_from_series(xd, scale)
+    nb = n // 2 + 1
+    offs = torch.arange(nseries + 1, dtype=torch.int64, device="cuda") * nb
+    zmax, dz, M, L = 20.0, 2.0, 64, 512
+    taps, bank = fd.make_bank(zmax, dz, M, L)
+    K = taps.shape[0]
+    planes = fd.correlate_batched(specs.view(-1), offs, bank, K, M, L)
+    torch.cuda.synchronize()
+    for b in range(nseries):
+        one = fd.correlate(fd.spectrum_from_series(xd[b].contiguous(), scale), bank, K, M, L)
+        torch.cuda.synchronize()
+        assert torch.equal(planes[K * nb * b:K * nb * (b + 1)].view(K, nb), one), b
