@@ -285,3 +285,31 @@ def candidates_batched(sums, offsets, K: int, H: int, threshold: float, capacity
     r = rec["r"] - offs[spec]
     order = np.lexsort((r, rec["row"], spec))
     return spec[order], r[order], rec["row"][order].copy(), rec["power"][order].copy(), n
+
+
+def search_batched(x, zmax: float, dz: float, M: int, L: int, max_fold: int, thresholds,
+                   capacity: int = 1 << 16):
+    """The search path of Sec. 3 on nseries equal-length device time series
+    (a float32 [nseries][n] tensor), each step one launch (per pass or fold)
+    for the whole batch: real-to-complex transforms scaled by 1/sqrt(n), the
+    planes, harmonic sums up to ``max_fold`` and the peaks of each fold above
+    ``thresholds[H]``.  Each spectrum keeps its Nyquist bin (n/2 + 1 bins),
+    as the batched transform packs them.  Returns {H: (series, r, row, power,
+    count)} with host arrays sorted by (series, row, r)."""
+    import torch
+    nseries, n = x.shape
+    nb = n // 2 + 1
+    specs = spectra_from_series(x, 1.0 / float(n) ** 0.5)
+    offs = torch.arange(nseries + 1, dtype=torch.int64, device=x.device) * nb
+    taps, bank = make_bank(zmax, dz, M, L, device=x.device)
+    K = taps.shape[0]
+    planes = correlate_batched(specs.view(-1), offs, bank, K, M, L)
+    folds = harmonic_sums_batched(planes, offs, K, max_fold)
+    out = {}
+    H = 1
+    for S in folds:
+        if H in thresholds:
+            out[H] = candidates_batched(S, offs, K, H, float(thresholds[H]), capacity)
+        H *= 2
+    return out
+

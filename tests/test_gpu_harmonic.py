@@ -339,3 +339,38 @@ def test_batched_folds_of_correlated_planes(fd):
             n = int(offs[b + 1] - offs[b])
             single = _from_scratch(fd, planes[K * offs[b]:K * offs[b + 1]].view(K, n), H)
             assert torch.equal(S[KH * pre[b]:KH * pre[b + 1]].view(KH, -1), single), (H, b)
+
+
+def test_search_batched_equals_per_series_path(fd):
+    """Four series, each with a pulsar at its own (r0, z0), searched in one
+    batched call: the candidate sets of every fold equal those of the
+    single-series kernels on the same n/2 + 1-bin spectra, and each series'
+    strongest 8-fold peak is its pulsar."""
+    n = 1 << 17
+    zmax, dz, M, L = 40.0, 2.0, 64, 512
+    pulsars = [(2000.02, 4.0), (3100.02, -2.0), (1500.02, 2.0), (2600.02, 0.0)]
+    xs = np.stack([syn.pulsed_series(10 + b, n, r0, z0, 8, 0.02)
+                   for b, (r0, z0) in enumerate(pulsars)])
+    xd = torch.from_numpy(xs).cuda()
+    thr = {1: 15.0, 2: 25.0, 8: 60.0}
+    res = fd.search_batched(xd, zmax, dz, M, L, 8, thr)
+    assert set(res) == set(thr)
+    taps, bank = fd.make_bank(zmax, dz, M, L)
+    K = taps.shape[0]
+    c = (K - 1) // 2
+    nb = n // 2 + 1
+    for b, (r0, z0) in enumerate(pulsars):
+        spec = fd.spectrum_from_series(xd[b].contiguous(), 1.0 / np.sqrt(n))
+        plane = fd.correlate(spec, bank, K, M, L)
+        folds = fd.harmonic_sums(plane, 8)
+        for H, S in zip((1, 2, 4, 8), folds):
+            if H not in thr:
+                continue
+            r1, row1, p1, n1 = fd.candidates(S, nb, K, H, thr[H])
+            sb, rb, rowb, pb, _ = res[H]
+            sel = sb == b
+            assert np.array_equal(rb[sel], r1) and np.array_equal(rowb[sel], row1), (b, H)
+            assert np.array_equal(pb[sel], p1), (b, H)
+        sel = res[8][0] == b
+        best = np.argmax(res[8][3][sel])
+        assert (res[8][2][sel][best] - c) * dz == z0 and res[8][1][sel][best] == int(round(r0))
