@@ -655,6 +655,67 @@ def bench_r2c(fdas, torch, steps: int):
     return out
 
 
+def bench_pipeline(fdas, torch, steps: int):
+    """The operational scenario of Sec. 6: 64 equal-length time series of
+    2^21 samples (64 us sampling, 134 s each) through the batched front end
+    and the batched correlation (85 x 256 taps, segment 2048), then also
+    harmonic folds 2..32 and the 32-fold candidates of every series.  The
+    count of series one GPU handles in real time is 64 x 134 s / time."""
+    import numpy as np
+
+    import fdas_synth as syn
+    n, S = 1 << 21, 64
+    nb = n // 2 + 1
+    base = torch.from_numpy(np.stack([syn.time_series(600 + b, n) for b in range(4)])).cuda()
+    x = base.repeat(S // 4, 1).contiguous().view(-1)
+    del base
+    spec = torch.empty(S * nb, dtype=torch.complex64, device="cuda")
+    rws = torch.empty(fdas.fdas_r2c_batched_workspace_bytes(n, S), dtype=torch.uint8,
+                      device="cuda")
+    K, M, L = 85, 256, 2048
+    taps, bank = fdas.make_bank(84.0, 2.0, M, L)
+    offs_h = np.arange(S + 1, dtype=np.int64) * nb
+    offs = torch.from_numpy(offs_h).cuda()
+    planes = torch.empty(K * S * nb, dtype=torch.float32, device="cuda")
+    cws = torch.empty(fdas.fdas_batched_workspace_bytes(S), dtype=torch.uint8, device="cuda")
+    folds_H = [2, 4, 8, 16, 32]
+    outs = []
+    for H in folds_H:
+        KH, _ = fdas.fdas_harmonic_shape(0, K, H)
+        outs.append(torch.empty(KH * int(fdas.fold_prefix(offs_h, H)[-1]), dtype=torch.float32,
+                                device="cuda"))
+    hws = torch.empty(fdas.fdas_harmonic_batched_workspace_bytes(S), dtype=torch.uint8,
+                      device="cuda")
+    cbuf = torch.empty((1 << 16) * 16, dtype=torch.uint8, device="cuda")
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def front_and_plane():
+        fdas.fdas_r2c_batched(x, n, S, 1.0 / float(n) ** 0.5, spec, rws)
+        fdas.fdas_correlate_batched(spec, offs, S, bank, K, M, L, planes, cws)
+
+    def whole():
+        front_and_plane()
+        for i, H in enumerate(folds_H):
+            fdas.fdas_harmonic_sum_batched(planes, offs, S, K, H, outs[i - 1] if i else None,
+                                           outs[i], hws)
+        fdas.fdas_find_candidates_batched(outs[-1], offs, S, K, 32, 80.0, cbuf, 1 << 16, count,
+                                          hws)
+
+    whole()
+    ms_p = _timed(torch, front_and_plane, max(steps // 2, 3))
+    ms_w = _timed(torch, whole, max(steps // 2, 3))
+    t_obs = n * 64e-6
+    out = {"workload": f"{S} series of 2^21 samples (64 us sampling), {K} templates x {M} taps, "
+                       f"segment {L}",
+           "r2c_and_planes_ms": ms_p, "whole_search_ms": ms_w,
+           "real_time_series_r2c_and_planes": round(S * t_obs / (ms_p * 1e-3)),
+           "real_time_series_whole_search": round(S * t_obs / (ms_w * 1e-3)),
+           "paper_P100_no_interbinning_n_2e21": {"64": 41645, "96": 26801}}
+    del x, spec, rws, planes, cws, outs, hws, cbuf
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_harmonic(fdas, torch, steps: int):
     """Harmonic sums of the headline plane (85 x 2^21, computed here by the
     correlation at L = 2048): folds H = 2, 4, ..., 32, each built on the
@@ -724,7 +785,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and forward+backward comparisons")
-    ap.add_argument("--extras", default="batched,fwd_bwd,large_zmax,interbin,sym,r2c,harmonic",
+    ap.add_argument("--extras", default="batched,fwd_bwd,large_zmax,interbin,sym,r2c,harmonic,pipeline",
                     help="comma-separated extra comparisons to run")
     ap.add_argument("--extra-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -844,7 +905,7 @@ def main() -> int:
     torch.cuda.empty_cache()
     extras = {"batched": bench_batched, "fwd_bwd": bench_fwd_bwd, "large_zmax": bench_workload5,
               "interbin": bench_interbin, "sym": bench_sym, "r2c": bench_r2c,
-              "harmonic": bench_harmonic}
+              "harmonic": bench_harmonic, "pipeline": bench_pipeline}
     for name in ([] if args.no_extras else [x for x in args.extras.split(",") if x]):
         out[name] = extras[name](fdas, torch, args.extra_steps)
         print(f"# {name}: {json.dumps(out[name])}", file=sys.stderr, flush=True)
