@@ -77,6 +77,27 @@ def test_emulated_forward_vs_oracle(emu, L, M, N, grid):
     assert _rel(plane, native.power(A, taps)) < TOL
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_emulated_forward_random_shapes(emu, seed):
+    # seeded random geometry: segment length, even tap count up to L/2,
+    # spectrum length (ragged tail, sometimes shorter than one segment),
+    # template count and persistent grid; the plane against the oracle
+    rng = np.random.default_rng(seed + 500)
+    L = int(rng.choice([256, 512, 1024, 2048]))
+    M = 2 * int(rng.integers(1, L // 4 + 1))
+    N = int(rng.integers(1, 3 * (L - M) + 7))
+    K = int(rng.integers(1, 6))
+    grid = int(rng.integers(0, 9))
+    A = syn.random_spectrum(seed + 900, N)
+    taps = syn.random_taps(seed + 901, K, M)
+    bank = _bank(emu, taps, L)
+    buf, plane = _guarded((K, N))
+    assert emu.fdas_correlate_ex(_p(A), ctypes.c_int64(N), _p(bank), K, M, L, _p(plane),
+                                 grid, None) == 0, (L, M, N, K, grid)
+    _check_guards(buf, plane)
+    assert _rel(plane, native.power(A, taps)) < TOL, (L, M, N, K, grid)
+
+
 def test_emulated_templates_forward_workload1_slice(emu):
     # the library's own templates and bank on a 4000-bin slice of workload 1
     w = syn.workload(1)
