@@ -16,6 +16,7 @@ import shutil
 import subprocess
 import sys
 import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -41,7 +42,7 @@ def build(verbose: bool = False) -> str:
     """Compile all sources and link libfdas.so (always rebuilds)."""
     cc = hipcc()
     with tempfile.TemporaryDirectory(prefix="fdas_build_") as tmp:
-        objs = []
+        cmds, objs = [], []
         for src in SOURCES:
             obj = os.path.join(tmp, os.path.splitext(src)[0] + ".o")
             cmd = [cc, f"--offload-arch={ARCH}", *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
@@ -50,8 +51,13 @@ def build(verbose: bool = False) -> str:
                 cmd.insert(2, "hip")
             if verbose:
                 print(" ".join(cmd), flush=True)
-            subprocess.run(cmd, check=True)
+            cmds.append(cmd)
             objs.append(obj)
+        # the sources compile independently: one compiler process each
+        workers = max(1, min(len(cmds), os.cpu_count() or 1))
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            for r in ex.map(lambda c: subprocess.run(c, check=True), cmds):
+                pass
         out_tmp = LIB + f".tmp{os.getpid()}"
         cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out_tmp, *objs]
         if verbose:

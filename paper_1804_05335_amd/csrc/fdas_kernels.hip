@@ -184,7 +184,11 @@ struct Fwd {
     // transforms run on the window's X (the half-bin row is loaded as soon
     // as the first has consumed the integer row) and the [K][2N] plane gets
     // the pair (|y_r|^2, |y_half_r|^2) in one 8-byte store.
-    template <bool IB, bool SYM = false, bool DUAL = false>
+    // DEAD: output slots m < DEAD and m >= E - DEAD hold no valid output in
+    // any lane (positions below M/2 or from L - M/2 on, which needs
+    // M/2 >= DEAD T); their power and stores are skipped, so the compiler
+    // also drops the last butterfly operations that feed only them.
+    template <bool IB, bool SYM = false, bool DUAL = false, int DEAD = 0>
     __device__ static void item(const float2* __restrict__ spec, int64_t N,
                                 const float2* __restrict__ bank, int K, int M, int64_t s, int z0,
                                 int z1, float* __restrict__ plane, const float2 (&tw)[NTW],
@@ -199,6 +203,7 @@ struct Fwd {
         F::template run<false>(X, la, lb, tw, t);
 
         static_assert(!(SYM && (IB || DUAL)), "the symmetric bank is for the plain plane");
+        static_assert(DEAD == 0 || !(IB || DUAL), "dead slots apply to the plain plane");
         // One template; MIR: H holds a mirrored row in load order (symmetric
         // bank, z < c), consumed reversed and conjugated.
         auto one = [&](int z, auto mir_tag) {
@@ -244,7 +249,7 @@ struct Fwd {
                 const float* row_q0 = plane + ((int64_t)z * N + out0 - M / 2);
                 const auto rs = seg_rsrc(row_q0, (M / 2 + nvalid) * 4);
 #pragma unroll
-                for (int m = 0; m < E; ++m) {
+                for (int m = DEAD; m < E - DEAD; ++m) {
                     const float p = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
                     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(p), rs,
                                                           seg_off<4>(t + T * m, M / 2), 0,
@@ -326,7 +331,7 @@ __device__ __forceinline__ void item_range(int64_t total, int64_t& i0, int64_t& 
 // interbinned plane ([K][2N]) instead of the plain one ([K][N]); SYM a bank
 // that stores only the z >= 0 rows; DUAL adds the half-bin bank bank2 and
 // writes interleaved [K][2N] pairs.
-template <int L, bool IB, bool SYM, bool DUAL>
+template <int L, bool IB, bool SYM, bool DUAL, int DEAD>
 __global__ __launch_bounds__(Fwd<L>::T, 2) void forward_kernel(
     const float2* __restrict__ spec, int64_t N, const float2* __restrict__ bank, int K, int M,
     int64_t nseg, float* __restrict__ plane, const float2* __restrict__ bank2)
@@ -349,8 +354,8 @@ __global__ __launch_bounds__(Fwd<L>::T, 2) void forward_kernel(
         const int64_t s = i / K;
         const int zs = (int)(i - s * K);
         const int ze = (int)min<int64_t>(K, zs + (i1 - i));
-        W::template item<IB, SYM, DUAL>(spec, N, bank, K, M, s, zs, ze, plane, tw, la, lb, t, H,
-                                         bank2);
+        W::template item<IB, SYM, DUAL, DEAD>(spec, N, bank, K, M, s, zs, ze, plane, tw, la, lb,
+                                               t, H, bank2);
         i += ze - zs;
     }
 }
@@ -404,7 +409,7 @@ __global__ __launch_bounds__(kScanThreads) void segment_scan_kernel(
     }
 }
 
-template <int L>
+template <int L, int DEAD>
 __global__ __launch_bounds__(Fwd<L>::T, 2) void batched_kernel(
     const float2* __restrict__ specs, const int64_t* __restrict__ offsets,
     const int64_t* __restrict__ segpre, int nspec, const float2* __restrict__ bank, int K,
@@ -435,8 +440,9 @@ __global__ __launch_bounds__(Fwd<L>::T, 2) void batched_kernel(
         }
         const int64_t off = offsets[lo];
         const int64_t Nb = offsets[lo + 1] - off;
-        W::template item<false>(specs + off, Nb, bank, K, M, tile - segpre[lo], zs, ze,
-                planes + (int64_t)K * off, tw, la, lb, t, H);
+        W::template item<false, false, false, DEAD>(specs + off, Nb, bank, K, M,
+                                                    tile - segpre[lo], zs, ze,
+                                                    planes + (int64_t)K * off, tw, la, lb, t, H);
         i += ze - zs;
     }
 }
@@ -677,23 +683,49 @@ static hipError_t resident_grid(Kern kernel, int threads, std::atomic<int>* cach
     return hipSuccess;
 }
 
-template <int L, bool IB, bool SYM, bool DUAL>
-static hipError_t launch_forward_L(const float2* spec, int64_t N, const float2* bank, int K,
-                                   int M, float* plane, int grid, const float2* bank2,
-                                   hipStream_t s)
+template <int L, bool IB, bool SYM, bool DUAL, int DEAD>
+static hipError_t launch_forward_LD(const float2* spec, int64_t N, const float2* bank, int K,
+                                    int M, float* plane, int grid, const float2* bank2,
+                                    hipStream_t s)
 {
     static std::atomic<int> cache[64];
     const int64_t nseg = (N + (L - M) - 1) / (L - M);
     if (grid <= 0) {
-        hipError_t e = resident_grid(forward_kernel<L, IB, SYM, DUAL>, Fwd<L>::T, cache, &grid);
+        hipError_t e = resident_grid(forward_kernel<L, IB, SYM, DUAL, DEAD>, Fwd<L>::T, cache,
+                                     &grid);
         if (e != hipSuccess)
             return e;
     }
     if ((int64_t)grid > nseg * K)
         grid = (int)(nseg * K);
-    hipLaunchKernelGGL((forward_kernel<L, IB, SYM, DUAL>), dim3(grid), dim3(Fwd<L>::T), 0, s,
-                       spec, N, bank, K, M, nseg, plane, bank2);
+    hipLaunchKernelGGL((forward_kernel<L, IB, SYM, DUAL, DEAD>), dim3(grid), dim3(Fwd<L>::T), 0,
+                       s, spec, N, bank, K, M, nseg, plane, bank2);
     return hipGetLastError();
+}
+
+// Output slots with no valid output in any lane at each end (0..2): the
+// first covers positions below T, the second below 2T, all inside M/2.
+template <int L>
+static int dead_slots(int M)
+{
+    const int d = (M / 2) / Fwd<L>::T;
+    return d < 2 ? d : 2;
+}
+
+template <int L, bool IB, bool SYM, bool DUAL>
+static hipError_t launch_forward_L(const float2* spec, int64_t N, const float2* bank, int K,
+                                   int M, float* plane, int grid, const float2* bank2,
+                                   hipStream_t s)
+{
+    if constexpr (IB || DUAL) {
+        return launch_forward_LD<L, IB, SYM, DUAL, 0>(spec, N, bank, K, M, plane, grid, bank2, s);
+    } else {
+        switch (dead_slots<L>(M)) {
+        case 0: return launch_forward_LD<L, IB, SYM, DUAL, 0>(spec, N, bank, K, M, plane, grid, bank2, s);
+        case 1: return launch_forward_LD<L, IB, SYM, DUAL, 1>(spec, N, bank, K, M, plane, grid, bank2, s);
+        default: return launch_forward_LD<L, IB, SYM, DUAL, 2>(spec, N, bank, K, M, plane, grid, bank2, s);
+        }
+    }
 }
 
 template <bool IB, bool SYM, bool DUAL>
@@ -734,20 +766,32 @@ hipError_t launch_forward_dual(const float2* spec, int64_t N, const float2* bank
                                                  bank_half, s);
 }
 
+template <int L, int DEAD>
+static hipError_t launch_batched_LD(const float2* specs, const int64_t* offsets, int nspec,
+                                    const float2* bank, int K, int M, float* planes,
+                                    int64_t* segpre, int grid, hipStream_t s)
+{
+    static std::atomic<int> cache[64];
+    if (grid <= 0) {
+        hipError_t e = resident_grid(batched_kernel<L, DEAD>, Fwd<L>::T, cache, &grid);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL((batched_kernel<L, DEAD>), dim3(grid), dim3(Fwd<L>::T), 0, s, specs,
+                       offsets, segpre, nspec, bank, K, M, planes);
+    return hipGetLastError();
+}
+
 template <int L>
 static hipError_t launch_batched_L(const float2* specs, const int64_t* offsets, int nspec,
                                    const float2* bank, int K, int M, float* planes,
                                    int64_t* segpre, int grid, hipStream_t s)
 {
-    static std::atomic<int> cache[64];
-    if (grid <= 0) {
-        hipError_t e = resident_grid(batched_kernel<L>, Fwd<L>::T, cache, &grid);
-        if (e != hipSuccess)
-            return e;
+    switch (dead_slots<L>(M)) {
+    case 0: return launch_batched_LD<L, 0>(specs, offsets, nspec, bank, K, M, planes, segpre, grid, s);
+    case 1: return launch_batched_LD<L, 1>(specs, offsets, nspec, bank, K, M, planes, segpre, grid, s);
+    default: return launch_batched_LD<L, 2>(specs, offsets, nspec, bank, K, M, planes, segpre, grid, s);
     }
-    hipLaunchKernelGGL(batched_kernel<L>, dim3(grid), dim3(Fwd<L>::T), 0, s, specs, offsets,
-                       segpre, nspec, bank, K, M, planes);
-    return hipGetLastError();
 }
 
 hipError_t launch_batched(const float2* specs, const int64_t* offsets, int nspec,
