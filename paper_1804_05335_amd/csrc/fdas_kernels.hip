@@ -476,7 +476,12 @@ struct Bwd {
     // for the accumulate step.  WANT_T is a compile-time switch: without the
     // taps gradient's transform the kernel needs ~80 fewer VGPRs, which buys
     // a third wave per SIMD.
-    template <bool WANT_T>
+    // EDGE (M/2 = T exactly): slot 0 holds the positions below M/2 and slot
+    // E-1 those from L - M/2 on in every lane.  No window owns them, so g is
+    // zero there (w is not read), and they are exactly the taps gradient's
+    // lags, which are then stored without a per-lane test; the compiler
+    // drops the transform outputs nothing reads.
+    template <bool WANT_T, bool EDGE = false>
     __device__ static void item(const float2* __restrict__ spec, int64_t N,
                                 const float2* __restrict__ bank, int M, int64_t s, int z0,
                                 int z1, const float* __restrict__ dLdP, bool want_A,
@@ -503,13 +508,17 @@ struct Bwd {
             float wv[E];
 #pragma unroll
             for (int m = 0; m < E; ++m)
-                wv[m] = 2.f * __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
-                                  rw, seg_off<4>(t + T * m, M / 2), 0, kNonTemporal));
+                wv[m] = (EDGE && (m == 0 || m == E - 1))
+                            ? 0.f
+                            : 2.f * __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                                        rw, seg_off<4>(t + T * m, M / 2), 0, kNonTemporal));
             float2 v[E];
             F::template run_mul<true, kMul>(X, Hc, v, la, lb, tw, t);     // y = IFFT(X H_z)
 #pragma unroll
             for (int m = 0; m < E; ++m)                                   // g = 2 w y
-                v[m] = make_float2(wv[m] * v[m].x, wv[m] * v[m].y);
+                v[m] = (EDGE && (m == 0 || m == E - 1))
+                           ? make_float2(0.f, 0.f)
+                           : make_float2(wv[m] * v[m].x, wv[m] * v[m].y);
             float2 Hn[E];
             const int zn = z + 1 < z1 ? z + 1 : z0;
             auto next = [&]() { W::load_row(Hn, bank, zn, t); };
@@ -524,13 +533,18 @@ struct Bwd {
             if constexpr (WANT_T) {
                 F::template run_mul<true, kMulConj>(X, v, v, la, lb, tw, t);  // IFFT(X conj(G))
                 float2* pz = partT + (int64_t)z * M;
+                if constexpr (EDGE) {
+                    pz[t + M / 2] = v[0];                                 // p = t < M/2
+                    pz[t] = v[E - 1];                                     // p - L + M/2 = t
+                } else {
 #pragma unroll
-                for (int m = 0; m < E; ++m) {
-                    const int p = t + T * m;
-                    if (p < M / 2)
-                        pz[p + M / 2] = v[m];
-                    else if (p >= L - M / 2)
-                        pz[p - L + M / 2] = v[m];
+                    for (int m = 0; m < E; ++m) {
+                        const int p = t + T * m;
+                        if (p < M / 2)
+                            pz[p + M / 2] = v[m];
+                        else if (p >= L - M / 2)
+                            pz[p - L + M / 2] = v[m];
+                    }
                 }
             }
 #pragma unroll
@@ -546,7 +560,7 @@ struct Bwd {
     }
 };
 
-template <int L, bool WANT_T>
+template <int L, bool WANT_T, bool EDGE>
 __global__ __launch_bounds__(Bwd<L>::T, WANT_T ? BwdGeometry<L>::kMinWaves
                                                : BwdGeometry<L>::kMinWavesSpec) void backward_kernel(
     const float2* __restrict__ spec, int64_t N, const float2* __restrict__ bank, int K, int M,
@@ -566,7 +580,7 @@ __global__ __launch_bounds__(Bwd<L>::T, WANT_T ? BwdGeometry<L>::kMinWaves
     const int z1 = min(K, z0 + zchunk);
     float2 H[Bk::E];
     Bk::W::load_row(H, bank, z0, t);
-    Bk::template item<WANT_T>(spec, N, bank, M, s, z0, z1, dLdP, want_A != 0,
+    Bk::template item<WANT_T, EDGE>(spec, N, bank, M, s, z0, z1, dLdP, want_A != 0,
                               partA + ((int64_t)c * nwin + s) * L, partT + s * (int64_t)K * M, tw,
                               la, lb, t, H);
 }
@@ -822,12 +836,19 @@ static hipError_t launch_backward_L(const float2* spec, int64_t N, const float2*
 {
     const int nzc = (K + zchunk - 1) / zchunk;
     const dim3 grid((unsigned)nwin, (unsigned)nzc);
-    if (want_T)
-        hipLaunchKernelGGL((backward_kernel<L, true>), grid, dim3(Bwd<L>::T), 0, s, spec, N, bank,
-                           K, M, zchunk, nwin, dLdP, want_A, partA, partT);
-    else
-        hipLaunchKernelGGL((backward_kernel<L, false>), grid, dim3(Bwd<L>::T), 0, s, spec, N,
+    // The edge specialisation pays off with the taps transform (fewer
+    // instructions and cycles); without it the compiler waits for the w
+    // loads early in the transform and the kernel ran slower, so the
+    // spectrum-only kernel keeps the general form.
+    if (want_T && M / 2 == Bwd<L>::T)
+        hipLaunchKernelGGL((backward_kernel<L, true, true>), grid, dim3(Bwd<L>::T), 0, s, spec, N,
                            bank, K, M, zchunk, nwin, dLdP, want_A, partA, partT);
+    else if (want_T)
+        hipLaunchKernelGGL((backward_kernel<L, true, false>), grid, dim3(Bwd<L>::T), 0, s, spec,
+                           N, bank, K, M, zchunk, nwin, dLdP, want_A, partA, partT);
+    else
+        hipLaunchKernelGGL((backward_kernel<L, false, false>), grid, dim3(Bwd<L>::T), 0, s, spec,
+                           N, bank, K, M, zchunk, nwin, dLdP, want_A, partA, partT);
     return hipGetLastError();
 }
 

@@ -147,8 +147,10 @@ def test_emulated_batched_equals_plain(emu):
 
 # (256, 32, 29131): 131 windows, so the taps-gradient reduction runs in two
 # window chunks
+# M = L/4 at 8 values per lane puts M/2 on exactly one lane slot at each end
+# (512/128, 1024/256, 2048/512): the kernels specialised for those edge slots
 @pytest.mark.parametrize("L,M,N", [(256, 32, 900), (512, 128, 600), (2048, 256, 2500),
-                                   (256, 32, 29131)])
+                                   (256, 32, 29131), (1024, 256, 1500), (2048, 512, 2600)])
 def test_emulated_backward_vs_oracle(emu, L, M, N):
     K = 3
     A = syn.random_spectrum(3 * L, N)
