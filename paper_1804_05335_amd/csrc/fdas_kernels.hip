@@ -203,7 +203,7 @@ struct Fwd {
         F::template run<false>(X, la, lb, tw, t);
 
         static_assert(!(SYM && (IB || DUAL)), "the symmetric bank is for the plain plane");
-        static_assert(DEAD == 0 || !(IB || DUAL), "dead slots apply to the plain plane");
+        static_assert(DEAD == 0 || !DUAL, "dead slots apply to the plain and interbinned planes");
         // One template; MIR: H holds a mirrored row in load order (symmetric
         // bank, z < c), consumed reversed and conjugated.
         auto one = [&](int z, auto mir_tag) {
@@ -268,8 +268,10 @@ struct Fwd {
                 const int lane = t & 63, wave = t >> 6;
                 float2* edge = la;
                 if (lane == 0) {
+                    // slots DEAD .. E - DEAD: the live ones and, one past
+                    // them, the spare output at L - M/2
 #pragma unroll
-                    for (int m = 0; m < E; ++m)
+                    for (int m = DEAD; m < E - DEAD + (DEAD > 0 ? 1 : 0); ++m)
                         edge[wave * (E + 1) + m] = v[m];
                 }
                 next();
@@ -281,7 +283,7 @@ struct Fwd {
                 const float* row_q0 = plane + 2 * ((int64_t)z * N + out0 - M / 2);
                 const auto rs = seg_rsrc(row_q0, (M / 2 + nvalid) * 8);
 #pragma unroll
-                for (int m = 0; m < E; ++m) {
+                for (int m = DEAD; m < E - DEAD; ++m) {
                     float bx = __int_as_float(
                         __builtin_amdgcn_ds_bpermute(src, __float_as_int(v[m].x)));
                     float by = __int_as_float(
@@ -731,7 +733,7 @@ static hipError_t launch_forward_L(const float2* spec, int64_t N, const float2* 
                                    int M, float* plane, int grid, const float2* bank2,
                                    hipStream_t s)
 {
-    if constexpr (IB || DUAL) {
+    if constexpr (DUAL) {
         return launch_forward_LD<L, IB, SYM, DUAL, 0>(spec, N, bank, K, M, plane, grid, bank2, s);
     } else {
         switch (dead_slots<L>(M)) {

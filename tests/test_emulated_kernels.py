@@ -176,8 +176,10 @@ def test_emulated_backward_vs_oracle(emu, L, M, N):
     assert np.array_equal(gA2, gA)
 
 
+# 2048/256 and 2048/512 leave one and two lane slots at each end without
+# valid outputs (the kernels skip them at compile time)
 @pytest.mark.parametrize("L,M,N,grid", [(256, 32, 1000, 0), (512, 64, 449, 3), (2048, 256, 1793, 0),
-                                        (256, 2, 37, 0)])
+                                        (256, 2, 37, 0), (2048, 512, 3100, 2)])
 def test_emulated_interbin_vs_oracle(emu, L, M, N, grid):
     from oracle import direct
     K = 3
