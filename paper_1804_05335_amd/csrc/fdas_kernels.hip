@@ -203,7 +203,6 @@ struct Fwd {
         F::template run<false>(X, la, lb, tw, t);
 
         static_assert(!(SYM && (IB || DUAL)), "the symmetric bank is for the plain plane");
-        static_assert(DEAD == 0 || !DUAL, "dead slots apply to the plain and interbinned planes");
         // One template; MIR: H holds a mirrored row in load order (symmetric
         // bank, z < c), consumed reversed and conjugated.
         auto one = [&](int z, auto mir_tag) {
@@ -216,13 +215,13 @@ struct Fwd {
                 F::template run_mul_hook<true, kMul>(X, H, v, la, lb, tw, t, half);
                 float p1[E];
 #pragma unroll
-                for (int m = 0; m < E; ++m)
+                for (int m = DEAD; m < E - DEAD; ++m)
                     p1[m] = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
                 F::template run_mul_hook<true, kMul>(X, H, v, la, lb, tw, t, next);
                 const float* row_q0 = plane + 2 * ((int64_t)z * N + out0 - M / 2);
                 const auto rs = seg_rsrc(row_q0, (M / 2 + nvalid) * 8);
 #pragma unroll
-                for (int m = 0; m < E; ++m) {
+                for (int m = DEAD; m < E - DEAD; ++m) {
                     const float p2 = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
                     const u32x2 pp = {__float_as_uint(p1[m]), __float_as_uint(p2)};
                     __builtin_amdgcn_raw_buffer_store_b64(pp, rs, seg_off<8>(t + T * m, M / 2), 0,
@@ -733,14 +732,10 @@ static hipError_t launch_forward_L(const float2* spec, int64_t N, const float2* 
                                    int M, float* plane, int grid, const float2* bank2,
                                    hipStream_t s)
 {
-    if constexpr (DUAL) {
-        return launch_forward_LD<L, IB, SYM, DUAL, 0>(spec, N, bank, K, M, plane, grid, bank2, s);
-    } else {
-        switch (dead_slots<L>(M)) {
-        case 0: return launch_forward_LD<L, IB, SYM, DUAL, 0>(spec, N, bank, K, M, plane, grid, bank2, s);
-        case 1: return launch_forward_LD<L, IB, SYM, DUAL, 1>(spec, N, bank, K, M, plane, grid, bank2, s);
-        default: return launch_forward_LD<L, IB, SYM, DUAL, 2>(spec, N, bank, K, M, plane, grid, bank2, s);
-        }
+    switch (dead_slots<L>(M)) {
+    case 0: return launch_forward_LD<L, IB, SYM, DUAL, 0>(spec, N, bank, K, M, plane, grid, bank2, s);
+    case 1: return launch_forward_LD<L, IB, SYM, DUAL, 1>(spec, N, bank, K, M, plane, grid, bank2, s);
+    default: return launch_forward_LD<L, IB, SYM, DUAL, 2>(spec, N, bank, K, M, plane, grid, bank2, s);
     }
 }
 
