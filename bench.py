@@ -29,6 +29,9 @@ HBM_PEAK_GBS = 8000.0                      # MI355X HBM3E, GB/s
 # FP32 vector peak without packed-FP32 instructions (the library is compiled without them):
 # 256 CUs x 64 FP32 lanes x 2 flop (FMA) x 2.4 GHz
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# VALU issue peak: 256 CUs x 4 SIMDs, each retiring one 64-lane instruction per
+# 4 clocks, i.e. 256 x 64 lane-instructions per clock at 2.4 GHz
+VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
 
 # LDS: 64 banks x 4 B per clock per CU (the bank structure the kernels' LDS
@@ -132,28 +135,55 @@ def hbm_stream(fdas, torch, nbytes: int, steps: int):
 
 
 def kernel_sources_hash() -> str:
+    """First 16 hex digits of the sha256 over every library source file (all
+    of csrc/, in name order), so a counter summary is tied to the sources of
+    whichever kernel it profiles."""
     h = hashlib.sha256()
-    for f in ("fdas_kernels.hip", "fdas_fft.hpp"):
-        with open(os.path.join(ROOT, "paper_1804_05335_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_1804_05335_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(name: str):
-    """HBM bytes per launch from a committed counter summary, or None if the
-    summary is absent or was taken from other kernel sources."""
+def read_summary(name: str):
+    """The `key: value` lines of a committed counter summary, or None if the
+    summary is absent or was taken from other library sources."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):
-        if ":" in line and not line.startswith("#"):
+        if ":" in line and not line.startswith(("#", "|", " ")):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_sources_hash") != kernel_sources_hash():
         return None
+    return vals
+
+
+def read_traffic(name: str):
+    """HBM bytes per launch from a committed counter summary, or None if the
+    summary is absent or was taken from other kernel sources."""
+    vals = read_summary(name)
+    if vals is None:
+        return None
     try:
         return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def read_valu(name: str):
+    """VALU instructions (wave-level) per launch from a committed counter
+    summary of the current sources, or None."""
+    vals = read_summary(name)
+    if vals is None:
+        return None
+    try:
+        return float(vals["valu_insts_per_launch"])
     except (KeyError, ValueError):
         return None
 
@@ -276,19 +306,22 @@ def _timed(torch, fn, steps):
 
 
 def autotune(fdas, torch, taps, K, M, specs, offs, nspec, planes):
-    """Segment length picked by the library's autotuner for this batch."""
+    """Launch shape (L, E, grid) the library's autotuner picks for this batch
+    (timed afresh: the on-disk cache is bypassed so the record reflects this
+    device)."""
     ws = torch.empty(fdas._lib.fdas_autotune_workspace_bytes(K, nspec), dtype=torch.uint8,
                      device="cuda")
-    L, _, ms = fdas._lib.fdas_autotune_batched(taps.contiguous(), K, M, specs, offs, nspec,
-                                               planes, ws)
+    t = fdas._lib.fdas_autotune_batched(taps.contiguous(), K, M, specs, offs, nspec, planes, ws,
+                                        flags=fdas._lib.TUNE_NO_CACHE)
     del ws
-    return L, ms
+    return t
 
 
 def bench_batched(fdas, torch, steps: int):
     """256 ragged spectra (2^18..2^21 bins), 85 x 256 taps: one persistent
-    launch, the same launch replayed from a captured graph, and a loop of
-    plain per-spectrum calls over the same data and plane layout."""
+    launch at the autotuned shape, the same launch replayed from a captured
+    graph, and a loop of plain per-spectrum calls over the same data and
+    plane layout at the same segment length."""
     import fdas_synth as syn
     w = syn.workload(3)
     packed, o = w.packed()
@@ -298,13 +331,17 @@ def bench_batched(fdas, torch, steps: int):
     del packed
     planes = torch.empty(K * int(o[-1]), dtype=torch.float32, device="cuda")
     taps, _ = fdas.make_bank(w.zmax, w.dz, M, 2048)
-    L, tuned_ms = autotune(fdas, torch, taps, K, M, specs, offs, len(w.spectra), planes)
+    tuned = autotune(fdas, torch, taps, K, M, specs, offs, len(w.spectra), planes)
+    L, E, grid = tuned["L"], tuned["E"], tuned["grid"]
     bank = fdas.prepare_bank(taps, L)
     ws = torch.empty(fdas.fdas_batched_workspace_bytes(len(w.spectra)), dtype=torch.uint8,
                      device="cuda")
     nspec = len(w.spectra)
 
     def batched():
+        fdas.fdas_correlate_batched_ex(specs, offs, nspec, bank, K, M, L, planes, E, grid, ws)
+
+    def batched_default():
         fdas.fdas_correlate_batched(specs, offs, nspec, bank, K, M, L, planes, ws)
 
     def plain():
@@ -315,6 +352,8 @@ def bench_batched(fdas, torch, steps: int):
 
     batched()
     ms_b = _timed(torch, batched, steps)
+    batched_default()
+    ms_d = _timed(torch, batched_default, steps)
     plain()
     ms_p = _timed(torch, plain, steps)
     g = torch.cuda.CUDAGraph()
@@ -333,10 +372,11 @@ def bench_batched(fdas, torch, steps: int):
                        f"x {M} taps, segment {L}",
            "points": pts,
            "batched_ms": ms_b, "batched_points_per_s": pts / ms_b * 1e3,
+           "batched_default_shape_ms": ms_d,
            "graph_replay_ms": ms_g, "graph_points_per_s": pts / ms_g * 1e3,
            "plain_loop_ms": ms_p, "plain_loop_points_per_s": pts / ms_p * 1e3,
            "speedup_batched_vs_plain": ms_p / ms_b,
-           "segment_autotuned": L, "autotune_trials_ms": tuned_ms}
+           "autotuned": tuned}
     del ws
     out["harmonic"] = _batched_harmonic(fdas, torch, planes, offs, o, K, steps)
     del specs, planes
@@ -454,11 +494,12 @@ def bench_fwd_bwd(fdas, torch, steps: int):
 
 def bench_workload5(fdas, torch, steps: int):
     """64 ragged spectra (2^21..2^22 bins), 201 templates x 512 taps, segment
-    8192: batched forward over all spectra, then the gradient w.r.t. every
-    input spectrum for Lw = sum w P.  The plane is freed before the adjoint
-    (which recomputes the segment FFTs instead of reading it), so the plane
-    and dLw/dP -- 2 x 156 GB together, more than the 288 GB of HBM -- are
-    never resident at the same time."""
+    8192: batched forward over all spectra (at both lane geometries of that
+    segment length, and at the autotuned shape), then the gradient w.r.t.
+    every input spectrum for Lw = sum w P in one batched adjoint call.  The
+    plane is freed before the adjoint (which recomputes the segment FFTs
+    instead of reading it), so the plane and dLw/dP -- 2 x 156 GB together,
+    more than the 288 GB of HBM -- are never resident at the same time."""
     import fdas_synth as syn
     w = syn.workload(5)
     packed, o = w.packed()
@@ -471,47 +512,48 @@ def bench_workload5(fdas, torch, steps: int):
     total = int(o[-1])
     planes = torch.empty(K * total, dtype=torch.float32, device="cuda")
     ws = torch.empty(fdas.fdas_batched_workspace_bytes(nspec), dtype=torch.uint8, device="cuda")
-
-    def fwd():
-        fdas.fdas_correlate_batched(specs, offs, nspec, bank, K, M, L, planes, ws)
-
-    fwd()
-    ms_spec = _timed(torch, fwd, steps)          # at the specified segment length
     L_spec = L
-    L, _ = autotune(fdas, torch, taps, K, M, specs, offs, nspec, planes)
+    per_E = {}
+    for E in (16, 8):
+        def fwd_e(E=E):
+            fdas.fdas_correlate_batched_ex(specs, offs, nspec, bank, K, M, L_spec, planes, E, 0, ws)
+        fwd_e()
+        per_E[E] = _timed(torch, fwd_e, steps)
+    tuned = autotune(fdas, torch, taps, K, M, specs, offs, nspec, planes)
+    L, E, grid = tuned["L"], tuned["E"], tuned["grid"]
     if L != L_spec:
         bank = fdas.prepare_bank(taps, L)
-        fwd()
-        ms_f = _timed(torch, fwd, steps)
-    else:
-        ms_f = ms_spec
+
+    def fwd():
+        fdas.fdas_correlate_batched_ex(specs, offs, nspec, bank, K, M, L, planes, E, grid, ws)
+
+    fwd()
+    ms_f = _timed(torch, fwd, steps)
     del planes
     torch.cuda.empty_cache()
     gen = torch.Generator(device="cuda")
     gen.manual_seed(5)
     wts = torch.rand(K * total, generator=gen, dtype=torch.float32, device="cuda")
     grads = torch.empty(total, dtype=torch.complex64, device="cuda")
-    nmax = int(max(o[b + 1] - o[b] for b in range(nspec)))
-    bws = torch.empty(fdas.fdas_backward_workspace_bytes(nmax, K, M, L, 0), dtype=torch.uint8,
-                      device="cuda")
+    bws = torch.empty(fdas.fdas_backward_batched_workspace_bytes(total, nspec, K, M, L, 0, 1),
+                      dtype=torch.uint8, device="cuda")
 
     def bwd():
-        for b in range(nspec):
-            n = int(o[b + 1] - o[b])
-            need = fdas.fdas_backward_workspace_bytes(n, K, M, L, 0)
-            fdas.fdas_correlate_backward(specs[o[b]:o[b + 1]], n, bank, K, M, L,
-                                         wts[K * o[b]:K * o[b + 1]], grads[o[b]:o[b + 1]], None,
-                                         bws[:need])
+        fdas.fdas_correlate_backward_batched(specs, offs, nspec, bank, K, M, L, wts, grads, None,
+                                             bws)
 
     bwd()
     ms_b = _timed(torch, bwd, max(1, steps // 2))
     pts = K * total
     out = {"workload": f"{nspec} ragged spectra (2^21..2^22 bins, sum {total}), {K} templates x "
-                       f"{M} taps, segment {L}",
+                       f"{M} taps, segment {L_spec} (configured) and {L} (autotuned)",
            "points": pts,
-           f"forward_batched_ms_segment_{L_spec}": ms_spec, "segment_autotuned": L,
+           f"forward_batched_ms_segment_{L_spec}": min(per_E.values()),
+           f"forward_batched_ms_segment_{L_spec}_per_values_per_lane": {str(k): v for k, v in per_E.items()},
+           "autotuned": tuned,
            "forward_batched_ms": ms_f, "forward_points_per_s": pts / ms_f * 1e3,
-           "backward_spec_ms": ms_b, "fwd_bwd_points_per_s": pts / (ms_f + ms_b) * 1e3,
+           "backward_spec_ms": ms_b, "backward_call": "fdas_correlate_backward_batched (one launch)",
+           "fwd_bwd_points_per_s": pts / (ms_f + ms_b) * 1e3,
            "backward_spec_roofline": roof_pair(
                *[sum(x) for x in zip(*(backward_work(int(o[b + 1] - o[b]), K, M, L, False)
                                        for b in range(nspec)))], ms_b),
@@ -852,29 +894,34 @@ def main() -> int:
           f"{K * N / ms / 1e9:.4f} Gpoints/s", file=sys.stderr, flush=True)
     bytes_, flops = forward_work(N, K, M, L)
     sec = ms / 1e3
-    ksec = ms_k / 1e3       # the roofline uses the kernel's own mean launch duration
+    ksec = ms_k / 1e3       # the rooflines use the kernel's own mean launch duration
+    summary = f"forward_L{L}_2e21x85_counters.md"
+    traffic = read_traffic(summary)
+    # HBM roof: algorithmic bytes per launch over the mean launch time
     hbm = {"bound": "hbm", "achieved": round(bytes_ / ksec / 1e9, 2), "peak": HBM_PEAK_GBS,
-           "unit": "GB/s"}
+           "unit": "GB/s", "traffic": traffic}
     hbm["frac"] = round(hbm["achieved"] / HBM_PEAK_GBS, 4)
-    alu = {"bound": "alu", "achieved": round(flops / ksec / 1e12, 3), "peak": round(ALU_PEAK_TFLOPS, 2),
-           "unit": "TFLOP/s"}
-    alu["frac"] = round(alu["achieved"] / alu["peak"], 4)
+    # beside it, the VALU issue roof from counted instructions: SQ_INSTS_VALU
+    # (wave instructions per launch, from the counter summary of the current
+    # sources) x 64 lanes over the launch time, against 256 CUs x 64 lanes x
+    # 2.4 GHz lane-instructions per second
+    valu = read_valu(summary)
+    alu = {"bound": "alu", "unit": "VALU lane-instructions/s", "peak": VALU_PEAK_LANE_OPS,
+           "valu_insts_per_launch": valu,
+           "achieved": None if valu is None else round(valu * 64 / ksec, -8)}
+    alu["frac"] = None if valu is None else round(alu["achieved"] / VALU_PEAK_LANE_OPS, 4)
+    alu["flop_model_TFLOPs"] = round(flops / ksec / 1e12, 3)
     lds_b = forward_lds_bytes(N, K, M, L)
     lds = {"bound": "lds", "achieved": round(lds_b / ksec / 1e9, 1), "peak": round(LDS_PEAK_GBS, 1),
            "unit": "GB/s", "bytes_per_launch": lds_b}
     lds["frac"] = round(lds["achieved"] / lds["peak"], 4)
-    traffic = read_traffic(f"forward_L{L}_2e21x85_counters.md")
-    for r in (hbm, alu):
-        r["traffic"] = traffic
-    # the binding roof is the one the kernel is closer to
-    roof, other = (alu, hbm) if alu["frac"] >= hbm["frac"] else (hbm, alu)
 
     stream_peaks = hbm_stream(fdas, torch, 4 << 30, max(5, args.steps // 2))
     print(f"# streaming probes: {json.dumps(stream_peaks)}", file=sys.stderr, flush=True)
     hbm["frac_of_measured_write"] = round(hbm["achieved"] / stream_peaks["write_GBps"], 4)
 
     out = {
-        "metric": "f-fdot points/s (templates x bins), fused FDAS forward correlation",
+        "metric": "f-fdot points/s (templates\u00d7bins) & HBM roofline %; batched, fwd+bwd vs plain",
         "value": K * N / sec,
         "unit": "points/s",
         "n_gpus": 1,
@@ -890,8 +937,8 @@ def main() -> int:
                                f"taps, segment L={L}",
                    "bins": N, "templates": K, "taps": M, "segment": L,
                    "grid": args.grid or "resident"},
-        "roofline": roof,
-        "roofline_other": other,
+        "roofline": hbm,
+        "roofline_alu": alu,
         "roofline_lds": lds,
         "kernel_ms": ms_k,
         "host_enqueue_ms": ms_host,

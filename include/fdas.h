@@ -239,10 +239,16 @@ size_t fdas_batched_workspace_bytes(int nspec);
  * still fill the device.
  *   specs_dev   : spectra packed back to back, 8-byte aligned; spectrum b is
  *                 specs_dev[offsets[b] .. offsets[b+1]);
- *   offsets_dev : DEVICE array of nspec + 1 int64, non-decreasing (a
- *                 negative length is treated as empty); read at execution
- *                 time, so a captured graph can be replayed for new batches
- *                 after the caller rewrites offsets and spectra in place;
+ *   offsets_dev : DEVICE array of nspec + 1 int64, non-decreasing; read at
+ *                 execution time, so a captured graph can be replayed for new
+ *                 batches after the caller rewrites offsets and spectra in
+ *                 place;
+ *   capacity    : elements specs_dev holds (planes_dev holds K * capacity
+ *                 floats), 0 <= capacity <= 2^40.  Since the offsets are read
+ *                 on the device, the kernels clamp every offset to
+ *                 [0, capacity]: a spectrum reaching past the capacity is
+ *                 cut there and a negative length is empty, so no access
+ *                 leaves the buffers whatever the offsets hold;
  *   planes_dev  : plane b starts at planes_dev + K * offsets[b], layout
  *                 [K][N_b] row-major (so K * offsets[nspec] floats in all);
  *   ws_dev      : device workspace of ws_bytes >= fdas_batched_workspace_bytes
@@ -253,15 +259,23 @@ size_t fdas_batched_workspace_bytes(int nspec);
  * no host-side wait, allocation or memset, so it can be captured in a graph.
  */
 int fdas_correlate_batched(const fdas_cf32 *specs_dev, const int64_t *offsets_dev, int nspec,
-                           const fdas_cf32 *bank_dev, int K, int M, int L, float *planes_dev,
-                           void *ws_dev, size_t ws_bytes, hipStream_t stream);
+                           int64_t capacity, const fdas_cf32 *bank_dev, int K, int M, int L,
+                           float *planes_dev, void *ws_dev, size_t ws_bytes, hipStream_t stream);
 
-/* Same with an explicit number of persistent workgroups (0 = as many as the
- * device holds resident; at most 2^20). */
+/*
+ * Same with an explicit launch shape (what fdas_autotune_batched chooses):
+ *   E    : complex values per lane of the segment transforms, 0 = the
+ *          default (4 at L = 256, 8 at L = 512, 16 from L = 1024); 8 and 16
+ *          are both available from L = 1024 on, else FDAS_UNSUPPORTED.  A
+ *          different E changes the radix plan and so the FP32 rounding of
+ *          the plane, not its definition;
+ *   grid : persistent workgroups (0 = as many as the device holds resident;
+ *          at most 2^20); the plane does not depend on it.
+ */
 int fdas_correlate_batched_ex(const fdas_cf32 *specs_dev, const int64_t *offsets_dev,
-                              int nspec, const fdas_cf32 *bank_dev, int K, int M, int L,
-                              float *planes_dev, int grid, void *ws_dev, size_t ws_bytes,
-                              hipStream_t stream);
+                              int nspec, int64_t capacity, const fdas_cf32 *bank_dev, int K,
+                              int M, int L, float *planes_dev, int E, int grid, void *ws_dev,
+                              size_t ws_bytes, hipStream_t stream);
 
 /* Bytes of device workspace for fdas_correlate_backward(_ex) with the same
  * (N, K, M, L, zchunk; 0 = default), a multiple of 256; 0 for an invalid
@@ -301,26 +315,111 @@ int fdas_correlate_backward_ex(const fdas_cf32 *spec_dev, int64_t N, const fdas_
                                fdas_cf32 *grad_spec_dev, fdas_cf32 *grad_taps_dev, int zchunk,
                                void *ws_dev, size_t ws_bytes, hipStream_t stream);
 
+/* Gradients a batched adjoint call computes (fdas_backward_batched_workspace_bytes). */
+#define FDAS_WANT_SPECTRA 1
+#define FDAS_WANT_TAPS 2
+
+/*
+ * Bytes of device workspace for fdas_correlate_backward_batched with the
+ * same (capacity, nspec, K, M, L, zchunk) and the gradients in `want`
+ * (FDAS_WANT_SPECTRA | FDAS_WANT_TAPS); 0 for an invalid geometry.  With W =
+ * capacity / (L - M) + nspec (a bound on the batch's windows) and
+ * nzc = ceil(K / zchunk): nspec + 1 int64, then nzc * W * L complex values
+ * for the spectra's gradient and W * K * M complex values plus up to 2048 /
+ * ceil(K M / 64) FP64 chunk sums of K * M for the taps' gradient.
+ */
+size_t fdas_backward_batched_workspace_bytes(int64_t capacity, int nspec, int K, int M, int L,
+                                             int zchunk, int want);
+
+/*
+ * Adjoint of fdas_correlate_batched for Lw = sum_b sum_{z,r} w_b[z][r]
+ * P_b[z][r] (not in the paper; the single-spectrum adjoint of
+ * fdas_correlate_backward applied to every spectrum of the batch), in one
+ * persistent launch of a fixed grid over the (window, template chunk) items
+ * of all spectra, plus a scan and the FP64 reductions; offsets are read on
+ * the device, so the call makes no host wait, allocation or memset (for
+ * nspec >= 1) and can be captured in a graph.
+ *   specs_dev, offsets_dev, nspec, capacity : as fdas_correlate_batched
+ *                   (offsets clamped to [0, capacity]);
+ *   bank_dev      : prepared bank for (K, M, L);
+ *   dLdP_dev      : w, packed like the planes: w_b at dLdP_dev + K *
+ *                   offsets[b], [K][N_b] row-major (K * capacity floats);
+ *   grad_specs_dev: capacity complex outputs packed like the spectra (bins
+ *                   outside every spectrum are set to 0), or NULL;
+ *   grad_taps_dev : K*M complex outputs, the taps gradient summed over the
+ *                   whole batch in FP64 in a fixed order, or NULL;
+ *   zchunk        : templates per work item (0 = default);
+ *   ws_dev        : >= fdas_backward_batched_workspace_bytes(capacity,
+ *                   nspec, K, M, L, zchunk, want) bytes for the gradients
+ *                   requested, 256-byte aligned; scratch.
+ * Each spectrum's grad_specs is bitwise the one fdas_correlate_backward_ex
+ * gives for that spectrum alone with the same zchunk; grad_taps equals the
+ * sum of the single-spectrum taps gradients up to FP32 rounding.  Offsets
+ * must be non-decreasing for these results (overlapping ranges give
+ * unspecified values but no access outside the buffers).  Both gradients
+ * NULL is a no-op; nspec = 0 writes zero gradients.
+ */
+int fdas_correlate_backward_batched(const fdas_cf32 *specs_dev, const int64_t *offsets_dev,
+                                    int nspec, int64_t capacity, const fdas_cf32 *bank_dev, int K,
+                                    int M, int L, const float *dLdP_dev,
+                                    fdas_cf32 *grad_specs_dev, fdas_cf32 *grad_taps_dev,
+                                    int zchunk, void *ws_dev, size_t ws_bytes, hipStream_t stream);
+
 /* Bytes of device workspace fdas_autotune_batched needs: a bank for the
  * largest segment length plus the batched workspace. */
 size_t fdas_autotune_workspace_bytes(int K, int nspec);
 
+/* A launch shape of the batched forward and, from the tuner, its time. */
+typedef struct {
+    int L;            /* segment length */
+    int E;            /* complex values per lane of the segment transforms */
+    int grid_factor;  /* persistent grid = grid_factor x resident workgroups */
+    int grid;         /* that grid as fdas_correlate_batched_ex takes it (0 = resident) */
+    int from_cache;   /* 1 if fdas_autotune_batched took the choice from a cache */
+    double ms;        /* measured ms per batched call (0 in a candidate list) */
+} fdas_tuning;
+
+/* fdas_autotune_batched flags */
+#define FDAS_TUNE_NO_CACHE 1   /* neither read nor write the process or file cache */
+#define FDAS_TUNE_REFRESH 2    /* time again and replace the cached choice */
+
+/*
+ * The launch shapes fdas_autotune_batched times for (K, M), in its order:
+ * every supported L from 512 to 8192 with M <= L/2, every E of that L
+ * (fdas_correlate_batched_ex) and grid factors 1 and 2.  Writes
+ * min(capacity, count) entries (grid = 0, ms = 0) and the full count.
+ * Host only.
+ */
+int fdas_autotune_candidates(int K, int M, fdas_tuning *list, int capacity, int *count);
+
+/* Workgroups of the batched kernel for (L, E, M) the current device holds
+ * resident: the grid a call with grid = 0 launches. */
+int fdas_batched_resident_grid(int L, int E, int M, int *grid);
+
 /*
  * Autotuner for the batched forward (the paper tunes the segment length and
  * launch shape per card by hand, Sec. 5.1.2): prepares a bank from taps_dev
- * for every supported L with M <= L/2, times fdas_correlate_batched on the
- * caller's batch (one warm-up launch, mean of three) and returns the fastest
- * L and persistent grid (*grid_out = 0: the resident workgroup count) and
- * its time in ms (ms_out may be NULL).  planes_dev is overwritten (it must
- * hold K * offsets[nspec] floats); ws_dev holds at least
+ * for every candidate L (fdas_autotune_candidates) and times
+ * fdas_correlate_batched_ex on the caller's batch for every candidate
+ * (L, E, grid) in two rounds (per round one warm-up launch and the mean of
+ * three; a candidate's better round counts), and writes the fastest to *out.
+ * The choice is cached for the life of the process and in a JSON file
+ * ($FDAS_TUNE_CACHE, an empty value disabling it; else
+ * $XDG_CACHE_HOME/fdas/autotune.json or ~/.cache/fdas/autotune.json; one
+ * entry per line, rewritten atomically), keyed by the device architecture,
+ * its compute-unit count, K, M and floor(log2) of the batch's total bins and
+ * of nspec; a cached choice is returned without timing (from_cache = 1)
+ * unless flags has FDAS_TUNE_REFRESH; FDAS_TUNE_NO_CACHE bypasses both
+ * caches.  offsets_dev/capacity as fdas_correlate_batched; planes_dev
+ * (K * capacity floats) is scratch for the trials: its contents afterwards
+ * are unspecified, on a cache hit as on a miss.  ws_dev holds at least
  * fdas_autotune_workspace_bytes(K, nspec) bytes (256-byte aligned).
- * Synchronises the stream; results are cached per (device, K, M, nspec,
- * log2 of the total bins) for the life of the process.  Not on the hot path.
+ * Synchronises the stream.  Not on the hot path.
  */
 int fdas_autotune_batched(const fdas_cf32 *taps_dev, int K, int M, const fdas_cf32 *specs_dev,
-                          const int64_t *offsets_dev, int nspec, float *planes_dev, void *ws_dev,
-                          size_t ws_bytes, hipStream_t stream, int *L_out, int *grid_out,
-                          double *ms_out);
+                          const int64_t *offsets_dev, int nspec, int64_t capacity,
+                          float *planes_dev, void *ws_dev, size_t ws_bytes, int flags,
+                          hipStream_t stream, fdas_tuning *out);
 
 /* ---- real-to-complex front end -------------------------------------------- */
 

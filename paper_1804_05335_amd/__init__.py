@@ -23,7 +23,9 @@ from ._lib import (FdasError, fdas_backward_workspace_bytes, fdas_bank_elems,  #
                    fdas_find_candidates, fdas_harmonic_batched_workspace_bytes,
                    fdas_harmonic_sum_batched, fdas_find_candidates_batched,
                    fdas_stream_write, fdas_stream_read, fdas_r2c_batched,
-                   fdas_r2c_batched_workspace_bytes, lib)
+                   fdas_r2c_batched_workspace_bytes, fdas_correlate_backward_batched,
+                   fdas_backward_batched_workspace_bytes, fdas_autotune_batched,
+                   fdas_autotune_candidates, fdas_batched_resident_grid, lib)
 
 
 def make_bank(zmax: float, dz: float, M: int, L: int, device="cuda"):
@@ -80,13 +82,14 @@ def pack(spectra, device="cuda"):
 
 
 def correlate_batched(specs, offsets, bank, K: int, M: int, L: int, planes=None, ws=None,
-                      grid: int = 0):
+                      grid: int = 0, E: int = 0):
     """Planes of packed spectra in one persistent launch.
 
     ``offsets`` is the device int64 tensor of nspec + 1 offsets; plane b is
     ``planes[K*offsets[b] : K*offsets[b+1]].view(K, N_b)``.  ``planes`` and
     the workspace ``ws`` are allocated when not given (pass them to keep the
-    call allocation-free, e.g. under graph capture).
+    call allocation-free, e.g. under graph capture).  ``E`` and ``grid`` are
+    the launch shape (0 = defaults; see fdas_autotune_batched).
     """
     import torch
     from ._lib import fdas_batched_workspace_bytes, fdas_correlate_batched_ex
@@ -97,8 +100,29 @@ def correlate_batched(specs, offsets, bank, K: int, M: int, L: int, planes=None,
     if ws is None:
         ws = torch.empty(max(fdas_batched_workspace_bytes(nspec), 1), dtype=torch.uint8,
                          device=specs.device)
-    fdas_correlate_batched_ex(specs, offsets, nspec, bank, K, M, L, planes, grid, ws)
+    fdas_correlate_batched_ex(specs, offsets, nspec, bank, K, M, L, planes, E, grid, ws)
     return planes
+
+
+def correlate_backward_batched(specs, offsets, bank, K: int, M: int, L: int, dLdP,
+                               want_spectra: bool = True, want_taps: bool = True, ws=None,
+                               zchunk: int = 0):
+    """Gradients of Lw = sum_b sum w_b P_b for a packed batch: (grad_specs
+    packed like ``specs`` or None, grad_taps [K][M] summed over the batch or
+    None).  ``dLdP`` is packed like the planes of correlate_batched."""
+    import torch
+    nspec = offsets.numel() - 1
+    cap = min(specs.numel(), dLdP.numel() // K)
+    gs = torch.empty(cap, dtype=torch.complex64, device=specs.device) if want_spectra else None
+    gt = torch.empty((K, M), dtype=torch.complex64, device=specs.device) if want_taps else None
+    want = (1 if want_spectra else 0) | (2 if want_taps else 0)
+    if ws is None:
+        ws = torch.empty(max(fdas_backward_batched_workspace_bytes(cap, nspec, K, M, L, zchunk,
+                                                                   want), 1),
+                         dtype=torch.uint8, device=specs.device)
+    fdas_correlate_backward_batched(specs, offsets, nspec, bank, K, M, L, dLdP, gs, gt, ws,
+                                    zchunk)
+    return gs, gt
 
 
 def spectrum_from_series(x, scale: float = 1.0, spec=None, ws=None):

@@ -41,12 +41,16 @@ SIGNATURES = [
     ("fdas_correlate_interbin", _I, [_P, _I64, _P, _I, _I, _I, _P, _P]),
     ("fdas_correlate_interbin_ex", _I, [_P, _I64, _P, _I, _I, _I, _P, _I, _P]),
     ("fdas_batched_workspace_bytes", _SZ, [_I]),
-    ("fdas_correlate_batched", _I, [_P, _P, _I, _P, _I, _I, _I, _P, _P, _SZ, _P]),
-    ("fdas_correlate_batched_ex", _I, [_P, _P, _I, _P, _I, _I, _I, _P, _I, _P, _SZ, _P]),
+    ("fdas_correlate_batched", _I, [_P, _P, _I, _I64, _P, _I, _I, _I, _P, _P, _SZ, _P]),
+    ("fdas_correlate_batched_ex", _I, [_P, _P, _I, _I64, _P, _I, _I, _I, _P, _I, _I, _P, _SZ,
+                                       _P]),
     ("fdas_autotune_workspace_bytes", _SZ, [_I, _I]),
-    ("fdas_autotune_batched", _I, [_P, _I, _I, _P, _P, _I, _P, _P, _SZ, _P,
-                                   ctypes.POINTER(_I), ctypes.POINTER(_I),
-                                   ctypes.POINTER(_D)]),
+    ("fdas_autotune_candidates", _I, [_I, _I, _P, _I, ctypes.POINTER(_I)]),
+    ("fdas_batched_resident_grid", _I, [_I, _I, _I, ctypes.POINTER(_I)]),
+    ("fdas_autotune_batched", _I, [_P, _I, _I, _P, _P, _I, _I64, _P, _P, _SZ, _I, _P, _P]),
+    ("fdas_backward_batched_workspace_bytes", _SZ, [_I64, _I, _I, _I, _I, _I, _I]),
+    ("fdas_correlate_backward_batched", _I, [_P, _P, _I, _I64, _P, _I, _I, _I, _P, _P, _P, _I,
+                                             _P, _SZ, _P]),
     ("fdas_backward_workspace_bytes", _SZ, [_I64, _I, _I, _I, _I]),
     ("fdas_correlate_backward", _I, [_P, _I64, _P, _I, _I, _I, _P, _P, _P, _P, _SZ, _P]),
     ("fdas_correlate_backward_ex", _I, [_P, _I64, _P, _I, _I, _I, _P, _P, _P, _I, _P, _SZ, _P]),
@@ -231,22 +235,29 @@ def fdas_batched_workspace_bytes(nspec: int) -> int:
     return int(lib().fdas_batched_workspace_bytes(nspec))
 
 
+def batched_capacity(specs, planes, K: int) -> int:
+    """Bins a packed batch's buffers hold: specs elements, and planes floats
+    over K (the call clamps the device offsets to this)."""
+    return min(specs.numel(), planes.numel() // K)
+
+
 def fdas_correlate_batched(specs, offsets, nspec: int, bank, K: int, M: int, L: int, planes,
                            ws, stream=None) -> None:
-    fdas_correlate_batched_ex(specs, offsets, nspec, bank, K, M, L, planes, 0, ws, stream)
+    fdas_correlate_batched_ex(specs, offsets, nspec, bank, K, M, L, planes, 0, 0, ws, stream)
 
 
 def fdas_correlate_batched_ex(specs, offsets, nspec: int, bank, K: int, M: int, L: int, planes,
-                              grid: int, ws, stream=None) -> None:
+                              E: int, grid: int, ws, stream=None) -> None:
     import torch
     _require(specs, torch.complex64, "specs")
     _require(offsets, torch.int64, "offsets", nspec + 1)
     _require(bank, torch.complex64, "bank", fdas_bank_elems(K, L))
     _require(planes, torch.float32, "planes")
     _require(ws, torch.uint8, "ws", fdas_batched_workspace_bytes(nspec))
-    _check(lib().fdas_correlate_batched_ex(_ptr(specs), _ptr(offsets), nspec, _ptr(bank), K, M, L,
-                                           _ptr(planes), grid, _ptr(ws),
-                                           ws.numel(), _stream(stream, specs)),
+    _check(lib().fdas_correlate_batched_ex(_ptr(specs), _ptr(offsets), nspec,
+                                           batched_capacity(specs, planes, K), _ptr(bank), K, M,
+                                           L, _ptr(planes), E, grid, _ptr(ws), ws.numel(),
+                                           _stream(stream, specs)),
            "fdas_correlate_batched")
 
 
@@ -276,25 +287,91 @@ def fdas_correlate_backward_ex(spec, N: int, bank, K: int, M: int, L: int, dLdP,
            "fdas_correlate_backward")
 
 
+def fdas_backward_batched_workspace_bytes(capacity: int, nspec: int, K: int, M: int, L: int,
+                                          zchunk: int = 0, want: int = 3) -> int:
+    """want: 1 = spectra gradient, 2 = taps gradient, 3 = both."""
+    return int(lib().fdas_backward_batched_workspace_bytes(capacity, nspec, K, M, L, zchunk, want))
+
+
+def fdas_correlate_backward_batched(specs, offsets, nspec: int, bank, K: int, M: int, L: int,
+                                    dLdP, grad_specs, grad_taps, ws, zchunk: int = 0,
+                                    stream=None) -> None:
+    """Adjoint of the batched forward: dLdP packed like the planes, grad_specs
+    like the spectra (or None), grad_taps [K][M] summed over the batch (or
+    None)."""
+    import torch
+    _require(specs, torch.complex64, "specs")
+    _require(offsets, torch.int64, "offsets", nspec + 1)
+    _require(bank, torch.complex64, "bank", fdas_bank_elems(K, L))
+    _require(dLdP, torch.float32, "dLdP")
+    cap = min(specs.numel(), dLdP.numel() // K)
+    if grad_specs is not None:
+        _require(grad_specs, torch.complex64, "grad_specs")
+        cap = min(cap, grad_specs.numel())
+    if grad_taps is not None:
+        _require(grad_taps, torch.complex64, "grad_taps", K * M)
+    want = (1 if grad_specs is not None else 0) | (2 if grad_taps is not None else 0)
+    _require(ws, torch.uint8, "ws",
+             fdas_backward_batched_workspace_bytes(cap, nspec, K, M, L, zchunk, want))
+    _check(lib().fdas_correlate_backward_batched(_ptr(specs), _ptr(offsets), nspec, cap,
+                                                 _ptr(bank), K, M, L, _ptr(dLdP),
+                                                 _ptr(grad_specs), _ptr(grad_taps), zchunk,
+                                                 _ptr(ws), ws.numel(), _stream(stream, specs)),
+           "fdas_correlate_backward_batched")
+
+
 def fdas_autotune_workspace_bytes(K: int, nspec: int) -> int:
     return int(lib().fdas_autotune_workspace_bytes(K, nspec))
 
 
+class Tuning(ctypes.Structure):
+    """fdas_tuning: a launch shape of the batched forward and its time."""
+    _fields_ = [("L", _I), ("E", _I), ("grid_factor", _I), ("grid", _I), ("from_cache", _I),
+                ("ms", _D)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+TUNE_NO_CACHE = 1
+TUNE_REFRESH = 2
+
+
+def fdas_autotune_candidates(K: int, M: int):
+    """The (L, E, grid_factor) shapes the autotuner times, in its order."""
+    n = _I(0)
+    _check(lib().fdas_autotune_candidates(K, M, None, 0, ctypes.byref(n)),
+           "fdas_autotune_candidates")
+    arr = (Tuning * n.value)()
+    _check(lib().fdas_autotune_candidates(K, M, ctypes.cast(arr, _P), n.value, ctypes.byref(n)),
+           "fdas_autotune_candidates")
+    return [a.as_dict() for a in arr]
+
+
+def fdas_batched_resident_grid(L: int, E: int, M: int) -> int:
+    g = _I(0)
+    _check(lib().fdas_batched_resident_grid(L, E, M, ctypes.byref(g)),
+           "fdas_batched_resident_grid")
+    return g.value
+
+
 def fdas_autotune_batched(taps, K: int, M: int, specs, offsets, nspec: int, planes, ws,
-                          stream=None):
-    """(L, grid, ms) of the fastest segment length for this batch."""
+                          flags: int = 0, stream=None) -> dict:
+    """The fastest launch shape for this batch: a dict with L, E, grid_factor,
+    grid (for fdas_correlate_batched_ex), from_cache and ms."""
     import torch
     _require(taps, torch.complex64, "taps", K * M)
     _require(specs, torch.complex64, "specs")
     _require(offsets, torch.int64, "offsets", nspec + 1)
     _require(planes, torch.float32, "planes")
     _require(ws, torch.uint8, "ws", fdas_autotune_workspace_bytes(K, nspec))
-    Lo, go, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0.0)
+    out = Tuning()
     _check(lib().fdas_autotune_batched(_ptr(taps), K, M, _ptr(specs), _ptr(offsets), nspec,
-                                       _ptr(planes), _ptr(ws), ws.numel(), _stream(stream, specs),
-                                       ctypes.byref(Lo), ctypes.byref(go), ctypes.byref(ms)),
+                                       batched_capacity(specs, planes, K), _ptr(planes),
+                                       _ptr(ws), ws.numel(), flags, _stream(stream, specs),
+                                       ctypes.byref(out)),
            "fdas_autotune_batched")
-    return Lo.value, go.value, ms.value
+    return out.as_dict()
 
 
 def fdas_r2c_workspace_bytes(n: int) -> int:

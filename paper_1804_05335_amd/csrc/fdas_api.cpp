@@ -51,6 +51,7 @@ constexpr int kMaxK = 4096;
 constexpr int64_t kMaxN = int64_t(1) << 32;
 constexpr int kMaxSpectra = 1 << 24;
 constexpr int kMaxGrid = 1 << 20;
+constexpr int64_t kMaxCapacity = int64_t(1) << 40;
 
 int check_grid(double zmax, double dz, int* K)
 {
@@ -428,16 +429,21 @@ size_t fdas_batched_workspace_bytes(int nspec)
 }
 
 int fdas_correlate_batched_ex(const fdas_cf32* specs_dev, const int64_t* offsets_dev, int nspec,
-                              const fdas_cf32* bank_dev, int K, int M, int L, float* planes_dev,
-                              int grid, void* ws_dev, size_t ws_bytes, hipStream_t stream)
+                              int64_t capacity, const fdas_cf32* bank_dev, int K, int M, int L,
+                              float* planes_dev, int E, int grid, void* ws_dev, size_t ws_bytes,
+                              hipStream_t stream)
 {
     int st = check_geometry(K, M, L);
     if (st)
         return st;
     if (nspec < 0 || nspec > kMaxSpectra)
         return fail(FDAS_INVALID_ARG, "nspec = %d outside [0, %d]", nspec, kMaxSpectra);
+    if (capacity < 0 || capacity > kMaxCapacity)
+        return fail(FDAS_INVALID_ARG, "capacity = %lld outside [0, 2^40]", (long long)capacity);
     if (grid < 0 || grid > kMaxGrid)
         return fail(FDAS_INVALID_ARG, "grid = %d outside [0, %d]", grid, kMaxGrid);
+    if (!fdas::batched_values_per_lane_ok(L, E))
+        return fail(FDAS_UNSUPPORTED, "E = %d values per lane is not supported at L = %d", E, L);
     if (nspec == 0)
         return ok();
     if (!specs_dev || !offsets_dev || !bank_dev || !planes_dev || !ws_dev)
@@ -450,8 +456,8 @@ int fdas_correlate_batched_ex(const fdas_cf32* specs_dev, const int64_t* offsets
         return fail(FDAS_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", ws_bytes,
                     fdas_batched_workspace_bytes(nspec));
     hipError_t e = fdas::launch_batched(reinterpret_cast<const float2*>(specs_dev), offsets_dev,
-                                        nspec, reinterpret_cast<const float2*>(bank_dev), K, M,
-                                        L, planes_dev, static_cast<int64_t*>(ws_dev), grid,
+                                        nspec, capacity, reinterpret_cast<const float2*>(bank_dev),
+                                        K, M, L, E, planes_dev, static_cast<int64_t*>(ws_dev), grid,
                                         stream);
     if (e != hipSuccess)
         return hip_fail(e, "batched launch");
@@ -459,11 +465,11 @@ int fdas_correlate_batched_ex(const fdas_cf32* specs_dev, const int64_t* offsets
 }
 
 int fdas_correlate_batched(const fdas_cf32* specs_dev, const int64_t* offsets_dev, int nspec,
-                           const fdas_cf32* bank_dev, int K, int M, int L, float* planes_dev,
-                           void* ws_dev, size_t ws_bytes, hipStream_t stream)
+                           int64_t capacity, const fdas_cf32* bank_dev, int K, int M, int L,
+                           float* planes_dev, void* ws_dev, size_t ws_bytes, hipStream_t stream)
 {
-    return fdas_correlate_batched_ex(specs_dev, offsets_dev, nspec, bank_dev, K, M, L,
-                                     planes_dev, 0, ws_dev, ws_bytes, stream);
+    return fdas_correlate_batched_ex(specs_dev, offsets_dev, nspec, capacity, bank_dev, K, M, L,
+                                     planes_dev, 0, 0, ws_dev, ws_bytes, stream);
 }
 
 namespace {
@@ -569,6 +575,99 @@ int fdas_correlate_backward(const fdas_cf32* spec_dev, int64_t N, const fdas_cf3
 {
     return fdas_correlate_backward_ex(spec_dev, N, bank_dev, K, M, L, dLdP_dev, grad_spec_dev,
                                       grad_taps_dev, 0, ws_dev, ws_bytes, stream);
+}
+
+namespace {
+
+// Upper bound on the windows of a batch whose spectra lie in [0, capacity):
+// sum_b ceil(N_b / B) <= capacity / B + nspec.
+int64_t batched_max_windows(int64_t capacity, int nspec, int B)
+{
+    return capacity / B + nspec;
+}
+
+// Batched adjoint workspace: winpre [nspec + 1] int64, then (if wanted)
+// partA [nzc][maxwin][L] complex, partT [maxwin][K][M] complex and tpart
+// [tsplit][K][M] FP64 complex, each 256-byte aligned.
+void backward_batched_layout(int64_t capacity, int nspec, int K, int M, int L, int zchunk,
+                             int want, size_t* offA, size_t* offT, size_t* offP, size_t* total)
+{
+    const int64_t maxwin = batched_max_windows(capacity, nspec, L - M);
+    const int zc = backward_zchunk(maxwin, K, zchunk);
+    const int64_t nzc = (K + zc - 1) / zc;
+    const size_t w = sizeof(int64_t) * ((size_t)nspec + 1);
+    const size_t a = (want & FDAS_WANT_SPECTRA)
+                         ? (size_t)nzc * (size_t)maxwin * (size_t)L * sizeof(fdas_cf32) : 0;
+    const size_t t = (want & FDAS_WANT_TAPS)
+                         ? (size_t)maxwin * (size_t)K * (size_t)M * sizeof(fdas_cf32) : 0;
+    const size_t p = (want & FDAS_WANT_TAPS) ? (size_t)backward_tsplit(maxwin, K, M) * (size_t)K *
+                                                   (size_t)M * 2 * sizeof(double)
+                                             : 0;
+    *offA = (w + 255) & ~(size_t)255;
+    *offT = ((*offA + a) + 255) & ~(size_t)255;
+    *offP = ((*offT + t) + 255) & ~(size_t)255;
+    *total = ((*offP + p) + 255) & ~(size_t)255;
+}
+
+}  // namespace
+
+size_t fdas_backward_batched_workspace_bytes(int64_t capacity, int nspec, int K, int M, int L,
+                                             int zchunk, int want)
+{
+    if (capacity < 0 || capacity > kMaxCapacity || nspec < 0 || nspec > kMaxSpectra ||
+        check_geometry(K, M, L) != FDAS_OK || zchunk < 0 || zchunk > K ||
+        (want & ~(FDAS_WANT_SPECTRA | FDAS_WANT_TAPS)))
+        return 0;
+    size_t offA = 0, offT = 0, offP = 0, total = 0;
+    backward_batched_layout(capacity, nspec, K, M, L, zchunk, want, &offA, &offT, &offP, &total);
+    return total < 256 ? 256 : total;
+}
+
+int fdas_correlate_backward_batched(const fdas_cf32* specs_dev, const int64_t* offsets_dev,
+                                    int nspec, int64_t capacity, const fdas_cf32* bank_dev, int K,
+                                    int M, int L, const float* dLdP_dev,
+                                    fdas_cf32* grad_specs_dev, fdas_cf32* grad_taps_dev,
+                                    int zchunk, void* ws_dev, size_t ws_bytes, hipStream_t stream)
+{
+    int st = check_geometry(K, M, L);
+    if (st)
+        return st;
+    if (nspec < 0 || nspec > kMaxSpectra)
+        return fail(FDAS_INVALID_ARG, "nspec = %d outside [0, %d]", nspec, kMaxSpectra);
+    if (capacity < 0 || capacity > kMaxCapacity)
+        return fail(FDAS_INVALID_ARG, "capacity = %lld outside [0, 2^40]", (long long)capacity);
+    if (zchunk < 0 || zchunk > K)
+        return fail(FDAS_INVALID_ARG, "zchunk = %d outside [0, K = %d]", zchunk, K);
+    if (!grad_specs_dev && !grad_taps_dev)
+        return ok();
+    if (!bank_dev || !ws_dev || !offsets_dev || (capacity > 0 && (!specs_dev || !dLdP_dev)))
+        return fail(FDAS_INVALID_ARG, "specs, offsets, bank, dLdP and ws must not be NULL");
+    if ((specs_dev && !aligned(specs_dev, 8)) || !aligned(offsets_dev, 8) ||
+        !aligned(bank_dev, 16) || (dLdP_dev && !aligned(dLdP_dev, 4)) ||
+        (grad_specs_dev && !aligned(grad_specs_dev, 8)) ||
+        (grad_taps_dev && !aligned(grad_taps_dev, 8)) || !aligned(ws_dev, 256))
+        return fail(FDAS_INVALID_ARG,
+                    "misaligned pointer (specs/offsets/grads 8 B, bank 16 B, dLdP 4 B, ws 256 B)");
+    const int want = (grad_specs_dev ? FDAS_WANT_SPECTRA : 0) | (grad_taps_dev ? FDAS_WANT_TAPS : 0);
+    const size_t need = fdas_backward_batched_workspace_bytes(capacity, nspec, K, M, L, zchunk, want);
+    if (ws_bytes < need)
+        return fail(FDAS_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", ws_bytes,
+                    need);
+    const int64_t maxwin = batched_max_windows(capacity, nspec, L - M);
+    const int zc = backward_zchunk(maxwin, K, zchunk);
+    size_t offA = 0, offT = 0, offP = 0, total = 0;
+    backward_batched_layout(capacity, nspec, K, M, L, zchunk, want, &offA, &offT, &offP, &total);
+    auto* base = static_cast<unsigned char*>(ws_dev);
+    hipError_t e = fdas::launch_backward_batched(
+        reinterpret_cast<const float2*>(specs_dev), offsets_dev, nspec, capacity,
+        reinterpret_cast<const float2*>(bank_dev), K, M, L, dLdP_dev,
+        reinterpret_cast<float2*>(grad_specs_dev), reinterpret_cast<float2*>(grad_taps_dev), zc,
+        maxwin, reinterpret_cast<int64_t*>(base), reinterpret_cast<float2*>(base + offA),
+        reinterpret_cast<float2*>(base + offT), backward_tsplit(maxwin, K, M),
+        reinterpret_cast<double2*>(base + offP), stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "batched backward launch");
+    return ok();
 }
 
 }  // extern "C"

@@ -34,9 +34,15 @@ hipError_t launch_forward_dual(const float2* spec, int64_t N, const float2* bank
 
 // Batched ragged correlation: segment scan into segpre[nspec + 1] (device
 // workspace), then the persistent kernel on `grid` workgroups (0 = fill the
-// device at full occupancy).
-hipError_t launch_batched(const float2* specs, const int64_t* offsets, int nspec,
-                          const float2* bank, int K, int M, int L, float* planes,
+// device at full occupancy) with E values per lane (0 = the default for L;
+// batched_values_per_lane_ok lists the others).  Offsets are clamped to
+// [0, cap] on the device.
+bool batched_values_per_lane_ok(int L, int E);
+// Workgroups of the batched kernel for (L, E, M) the current device holds
+// resident (the grid that `grid = 0` launches).
+hipError_t batched_resident_grid(int L, int E, int M, int* grid);
+hipError_t launch_batched(const float2* specs, const int64_t* offsets, int nspec, int64_t cap,
+                          const float2* bank, int K, int M, int L, int E, float* planes,
                           int64_t* segpre, int grid, hipStream_t s);
 
 // Adjoint: window kernel into partA [nzc][nwin][L] / partT [nwin][K][M], then
@@ -47,6 +53,18 @@ hipError_t launch_backward(const float2* spec, int64_t N, const float2* bank, in
                           int L, const float* dLdP, float2* grad_spec, float2* grad_taps,
                           int zchunk, float2* partA, float2* partT, int tsplit, double2* tpart,
                           hipStream_t s);
+
+// Batched adjoint over the spectra of a batched forward: window scan into
+// winpre [nspec + 1], the persistent window kernel into partA
+// [nzc][maxwin][L] / partT [maxwin][K][M] (maxwin bounds the windows of the
+// batch), then the reductions into grad_specs [cap] (packed like the
+// spectra; bins outside every spectrum get 0) and grad_taps [K][M] (summed
+// over the whole batch); either output may be null.
+hipError_t launch_backward_batched(const float2* specs, const int64_t* offsets, int nspec,
+                                   int64_t cap, const float2* bank, int K, int M, int L,
+                                   const float* dLdP, float2* grad_specs, float2* grad_taps,
+                                   int zchunk, int64_t maxwin, int64_t* winpre, float2* partA,
+                                   float2* partT, int tsplit, double2* tpart, hipStream_t s);
 
 // Real-to-complex front end (fdas_r2c.hip).  r2c_plan: radix bits per
 // global pass for N = 2^log2N complex points (pass count, or -1 if

@@ -370,12 +370,28 @@ __global__ __launch_bounds__(Fwd<L>::T, 2) void forward_kernel(
 // (segpre[nspec] = total segments); the persistent kernel then splits the
 // flattened (segment, template) items of all spectra into contiguous ranges,
 // so one launch of a fixed grid covers any batch and every workgroup reaches
-// the end of its range.
+// the end of its range.  The offsets are read on the device, so every use
+// clamps them to the caller's capacity (the bins specs holds; planes holds K
+// times as many floats): an offset past it, or a negative length, makes the
+// spectrum shorter or empty, never an access outside the buffers.
 
 constexpr int kScanThreads = 1024;
 
+// Spectrum b's first packed bin and length, clamped to [0, cap].
+__device__ __forceinline__ void spec_range(const int64_t* __restrict__ offsets, int b, int64_t cap,
+                                           int64_t& off, int64_t& n)
+{
+    int64_t o0 = offsets[b], o1 = offsets[b + 1];
+    o0 = o0 < 0 ? 0 : (o0 > cap ? cap : o0);
+    o1 = o1 < o0 ? o0 : (o1 > cap ? cap : o1);
+    off = o0;
+    n = o1 - o0;
+}
+
+// segpre[b + 1] = sum over b' <= b of ceil(N_b' / B) (segments of length B,
+// or the adjoint's windows, which have the same count).
 __global__ __launch_bounds__(kScanThreads) void segment_scan_kernel(
-    const int64_t* __restrict__ offsets, int nspec, int B, int64_t* __restrict__ segpre)
+    const int64_t* __restrict__ offsets, int nspec, int64_t cap, int B, int64_t* __restrict__ segpre)
 {
     __shared__ int64_t part[kScanThreads];
     __shared__ int64_t carry;
@@ -389,8 +405,9 @@ __global__ __launch_bounds__(kScanThreads) void segment_scan_kernel(
         const int b = base + t;
         int64_t segs = 0;
         if (b < nspec) {
-            const int64_t n = offsets[b + 1] - offsets[b];
-            segs = n > 0 ? (n + B - 1) / B : 0;
+            int64_t off, n;
+            spec_range(offsets, b, cap, off, n);
+            segs = (n + B - 1) / B;
         }
         part[t] = segs;
         __syncthreads();
@@ -410,13 +427,25 @@ __global__ __launch_bounds__(kScanThreads) void segment_scan_kernel(
     }
 }
 
-template <int L, int DEAD>
-__global__ __launch_bounds__(Fwd<L>::T, 2) void batched_kernel(
-    const float2* __restrict__ specs, const int64_t* __restrict__ offsets,
-    const int64_t* __restrict__ segpre, int nspec, const float2* __restrict__ bank, int K,
-    int M, float* __restrict__ planes)
+// The spectrum that owns flattened segment `tile`: the last b with
+// segpre[b] <= tile (segpre is non-decreasing, segpre[0] = 0 <= tile).
+__device__ __forceinline__ int owner(const int64_t* __restrict__ segpre, int nspec, int64_t tile)
 {
-    using W = Fwd<L>;
+    int lo = 0, hi = nspec - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segpre[mid] <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int L, int E, int DEAD>
+__global__ __launch_bounds__((Fwd<L, E>::T), 2) void batched_kernel(
+    const float2* __restrict__ specs, const int64_t* __restrict__ offsets,
+    const int64_t* __restrict__ segpre, int nspec, int64_t cap, const float2* __restrict__ bank,
+    int K, int M, float* __restrict__ planes)
+{
+    using W = Fwd<L, E>;
     __shared__ float2 lds[2][LdsSize<L>::value];
     int64_t i, i1;
     item_range(segpre[nspec] * K, i, i1);
@@ -433,16 +462,11 @@ __global__ __launch_bounds__(Fwd<L>::T, 2) void batched_kernel(
         const int64_t tile = i / K;
         const int zs = (int)(i - tile * K);
         const int ze = (int)min<int64_t>(K, zs + (i1 - i));
-        // spectrum b: the last index with segpre[b] <= tile
-        int lo = 0, hi = nspec - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (segpre[mid] <= tile) lo = mid; else hi = mid - 1;
-        }
-        const int64_t off = offsets[lo];
-        const int64_t Nb = offsets[lo + 1] - off;
+        const int b = owner(segpre, nspec, tile);
+        int64_t off, Nb;
+        spec_range(offsets, b, cap, off, Nb);
         W::template item<false, false, false, DEAD>(specs + off, Nb, bank, K, M,
-                                                    tile - segpre[lo], zs, ze,
+                                                    tile - segpre[b], zs, ze,
                                                     planes + (int64_t)K * off, tw, la, lb, t, H);
         i += ze - zs;
     }
@@ -621,14 +645,16 @@ __global__ void reduce_grad_spec_kernel(const float2* __restrict__ partA, int64_
 constexpr int kTapsCols = 64, kTapsRows = 16;
 
 __global__ __launch_bounds__(kTapsCols * kTapsRows) void reduce_grad_taps_kernel(
-    const float2* __restrict__ partT, int64_t nwin, int64_t chunk, int KM,
-    double2* __restrict__ tpart)
+    const float2* __restrict__ partT, int64_t nwin, const int64_t* __restrict__ nwin_dev,
+    int64_t chunk, int KM, double2* __restrict__ tpart)
 {
     __shared__ double part[kTapsRows][kTapsCols][2];
     const int c = threadIdx.x % kTapsCols, q = threadIdx.x / kTapsCols;
     const int i = blockIdx.x * kTapsCols + c;
+    // batched: the windows actually present (a device count, at most nwin)
+    const int64_t nw = nwin_dev ? min(nwin, *nwin_dev) : nwin;
     const int64_t s0 = (int64_t)blockIdx.y * chunk;
-    const int64_t s1 = min(nwin, s0 + chunk);
+    const int64_t s1 = min(nw, s0 + chunk);
     double sr = 0.0, si = 0.0;
     if (i < KM)
         for (int64_t s = s0 + q; s < s1; s += kTapsRows) {
@@ -663,6 +689,109 @@ __global__ void reduce_grad_taps_final_kernel(const double2* __restrict__ tpart,
     }
     const double inv = 1.0 / (double)L;
     grad[i] = make_float2((float)(tr * inv), (float)(ti * inv));
+}
+
+// ---- batched adjoint -----------------------------------------------------------
+//
+// The adjoint over the spectra of a batched forward (packed as for
+// batched_kernel, dL/dP packed like the planes).  A window of spectrum b is
+// the same window as in the single-spectrum adjoint; windows of all spectra
+// are numbered globally by the scan winpre (windows per spectrum =
+// ceil(N_b / B), the segment count), and the persistent kernel walks the
+// flattened (window, template chunk) items in a grid-stride loop, so the grid
+// is fixed whatever the batch.  Items past maxwin (the host's bound on the
+// window count, which only offsets that overlap could exceed) are skipped, so
+// no partial buffer is overrun.
+template <int L, bool WANT_T, bool EDGE>
+__global__ __launch_bounds__(Bwd<L>::T, WANT_T ? BwdGeometry<L>::kMinWaves
+                                               : BwdGeometry<L>::kMinWavesSpec) void
+backward_batched_kernel(const float2* __restrict__ specs, const int64_t* __restrict__ offsets,
+                        const int64_t* __restrict__ winpre, int nspec, int64_t cap,
+                        const float2* __restrict__ bank, int K, int M, int zchunk, int64_t maxwin,
+                        const float* __restrict__ dLdP, int want_A, float2* __restrict__ partA,
+                        float2* __restrict__ partT)
+{
+    using Bk = Bwd<L>;
+    __shared__ float2 lds[2][LdsSize<L>::value];
+    const int nzc = (K + zchunk - 1) / zchunk;
+    const int64_t nw = min(winpre[nspec], maxwin);
+    const int64_t items = nw * nzc;
+    if ((int64_t)blockIdx.x >= items)
+        return;     // uniform across the workgroup, before any barrier
+    const int t = threadIdx.x;
+    float2 tw[Bk::NTW];
+    Bk::F::twiddles(tw, bank + (int64_t)K * L, t);
+    float2* la = lds[0];
+    float2* lb = lds[1];
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int64_t g = it / nzc;
+        const int c = (int)(it - g * nzc);
+        const int b = owner(winpre, nspec, g);
+        int64_t off, Nb;
+        spec_range(offsets, b, cap, off, Nb);
+        const int z0 = c * zchunk;
+        const int z1 = min(K, z0 + zchunk);
+        float2 H[Bk::E];
+        Bk::W::load_row(H, bank, z0, t);
+        Bk::template item<WANT_T, EDGE>(specs + off, Nb, bank, M, g - winpre[b], z0, z1,
+                                        dLdP + (int64_t)K * off, want_A != 0,
+                                        partA + ((int64_t)c * maxwin + g) * L,
+                                        partT + g * (int64_t)K * M, tw, la, lb, t, H);
+    }
+}
+
+// grad[k] for every packed bin k < cap: the bins of spectrum b (the last b
+// whose clamped range starts at or before k and contains it) sum their
+// windows' partials as reduce_grad_spec_kernel does, in the same (chunk,
+// window) order, so each spectrum's gradient is bitwise the single-spectrum
+// one; bins outside every spectrum get 0.
+__global__ void reduce_grad_spec_batched_kernel(const float2* __restrict__ partA,
+                                                const int64_t* __restrict__ offsets,
+                                                const int64_t* __restrict__ winpre, int nspec,
+                                                int64_t cap, int L, int M, int64_t maxwin,
+                                                int nzc, float2* __restrict__ grad)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= cap)
+        return;
+    if (nspec == 0) {
+        grad[k] = make_float2(0.f, 0.f);
+        return;
+    }
+    // the last spectrum whose (clamped) start is <= k
+    int lo = 0, hi = nspec - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        int64_t o = offsets[mid];
+        o = o < 0 ? 0 : (o > cap ? cap : o);
+        if (o <= k) lo = mid; else hi = mid - 1;
+    }
+    int64_t off, n;
+    spec_range(offsets, lo, cap, off, n);
+    if (k < off || k >= off + n) {
+        grad[k] = make_float2(0.f, 0.f);
+        return;
+    }
+    const int64_t kl = k - off;
+    const int B = L - M;
+    const int64_t nwin = (n + B - 1) / B;
+    int64_t s_hi = (kl + M / 2) / B;           // windows with s B - M/2 <= kl
+    if (s_hi > nwin - 1)
+        s_hi = nwin - 1;
+    const int64_t lo_num = kl + M / 2 - L;     // windows with s B - M/2 + L > kl
+    const int64_t s_lo = lo_num < 0 ? 0 : lo_num / B + 1;
+    double sr = 0.0, si = 0.0;
+    for (int c = 0; c < nzc; ++c)
+        for (int64_t s = s_lo; s <= s_hi; ++s) {
+            const int64_t g = winpre[lo] + s;
+            if (g >= maxwin)
+                continue;
+            const int64_t p = kl - (s * B - M / 2);
+            const float2 v = partA[((int64_t)c * maxwin + g) * L + p];
+            sr += v.x;
+            si += v.y;
+        }
+    grad[k] = make_float2((float)sr, (float)si);
 }
 
 // ---- launchers -------------------------------------------------------------------
@@ -720,10 +849,10 @@ static hipError_t launch_forward_LD(const float2* spec, int64_t N, const float2*
 
 // Output slots with no valid output in any lane at each end (0..2): the
 // first covers positions below T, the second below 2T, all inside M/2.
-template <int L>
+template <int L, int E = Geometry<L>::E>
 static int dead_slots(int M)
 {
-    const int d = (M / 2) / Fwd<L>::T;
+    const int d = (M / 2) / Fwd<L, E>::T;
     return d < 2 ? d : 2;
 }
 
@@ -777,50 +906,122 @@ hipError_t launch_forward_dual(const float2* spec, int64_t N, const float2* bank
                                                  bank_half, s);
 }
 
-template <int L, int DEAD>
-static hipError_t launch_batched_LD(const float2* specs, const int64_t* offsets, int nspec,
-                                    const float2* bank, int K, int M, float* planes,
-                                    int64_t* segpre, int grid, hipStream_t s)
+template <int L, int E, int DEAD>
+static hipError_t resident_batched_LD(int* grid)
 {
     static std::atomic<int> cache[64];
+    return resident_grid(batched_kernel<L, E, DEAD>, Fwd<L, E>::T, cache, grid);
+}
+
+template <int L, int E>
+static hipError_t resident_batched_LE(int M, int* grid)
+{
+    switch (dead_slots<L, E>(M)) {
+    case 0: return resident_batched_LD<L, E, 0>(grid);
+    case 1: return resident_batched_LD<L, E, 1>(grid);
+    default: return resident_batched_LD<L, E, 2>(grid);
+    }
+}
+
+template <int L>
+static hipError_t resident_batched_L(int E, int M, int* grid)
+{
+    constexpr int E0 = Geometry<L>::E;
+    if (E == 0 || E == E0)
+        return resident_batched_LE<L, E0>(M, grid);
+    if constexpr (L >= 1024) {
+        constexpr int E1 = E0 == 16 ? 8 : 16;
+        if (E == E1)
+            return resident_batched_LE<L, E1>(M, grid);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t batched_resident_grid(int L, int E, int M, int* grid)
+{
+    switch (L) {
+    case 256:  return resident_batched_L<256>(E, M, grid);
+    case 512:  return resident_batched_L<512>(E, M, grid);
+    case 1024: return resident_batched_L<1024>(E, M, grid);
+    case 2048: return resident_batched_L<2048>(E, M, grid);
+    case 4096: return resident_batched_L<4096>(E, M, grid);
+    case 8192: return resident_batched_L<8192>(E, M, grid);
+    default:   return hipErrorInvalidValue;
+    }
+}
+
+template <int L, int E, int DEAD>
+static hipError_t launch_batched_LD(const float2* specs, const int64_t* offsets, int nspec,
+                                    int64_t cap, const float2* bank, int K, int M, float* planes,
+                                    int64_t* segpre, int grid, hipStream_t s)
+{
     if (grid <= 0) {
-        hipError_t e = resident_grid(batched_kernel<L, DEAD>, Fwd<L>::T, cache, &grid);
+        hipError_t e = resident_batched_LD<L, E, DEAD>(&grid);
         if (e != hipSuccess)
             return e;
     }
-    hipLaunchKernelGGL((batched_kernel<L, DEAD>), dim3(grid), dim3(Fwd<L>::T), 0, s, specs,
-                       offsets, segpre, nspec, bank, K, M, planes);
+    hipLaunchKernelGGL((batched_kernel<L, E, DEAD>), dim3(grid), dim3(Fwd<L, E>::T), 0, s, specs,
+                       offsets, segpre, nspec, cap, bank, K, M, planes);
     return hipGetLastError();
+}
+
+template <int L, int E>
+static hipError_t launch_batched_LE(const float2* specs, const int64_t* offsets, int nspec,
+                                    int64_t cap, const float2* bank, int K, int M, float* planes,
+                                    int64_t* segpre, int grid, hipStream_t s)
+{
+    switch (dead_slots<L, E>(M)) {
+    case 0: return launch_batched_LD<L, E, 0>(specs, offsets, nspec, cap, bank, K, M, planes, segpre, grid, s);
+    case 1: return launch_batched_LD<L, E, 1>(specs, offsets, nspec, cap, bank, K, M, planes, segpre, grid, s);
+    default: return launch_batched_LD<L, E, 2>(specs, offsets, nspec, cap, bank, K, M, planes, segpre, grid, s);
+    }
 }
 
 template <int L>
 static hipError_t launch_batched_L(const float2* specs, const int64_t* offsets, int nspec,
-                                   const float2* bank, int K, int M, float* planes,
-                                   int64_t* segpre, int grid, hipStream_t s)
+                                   int64_t cap, const float2* bank, int K, int M, int E,
+                                   float* planes, int64_t* segpre, int grid, hipStream_t s)
 {
-    switch (dead_slots<L>(M)) {
-    case 0: return launch_batched_LD<L, 0>(specs, offsets, nspec, bank, K, M, planes, segpre, grid, s);
-    case 1: return launch_batched_LD<L, 1>(specs, offsets, nspec, bank, K, M, planes, segpre, grid, s);
-    default: return launch_batched_LD<L, 2>(specs, offsets, nspec, bank, K, M, planes, segpre, grid, s);
+    constexpr int E0 = Geometry<L>::E;
+    if (E == 0 || E == E0)
+        return launch_batched_LE<L, E0>(specs, offsets, nspec, cap, bank, K, M, planes, segpre, grid, s);
+    if constexpr (L >= 1024) {
+        constexpr int E1 = E0 == 16 ? 8 : 16;
+        if (E == E1)
+            return launch_batched_LE<L, E1>(specs, offsets, nspec, cap, bank, K, M, planes, segpre, grid, s);
     }
+    return hipErrorInvalidValue;
 }
 
-hipError_t launch_batched(const float2* specs, const int64_t* offsets, int nspec,
-                          const float2* bank, int K, int M, int L, float* planes,
+bool batched_values_per_lane_ok(int L, int E)
+{
+    if (E == 0)
+        return true;
+    if (L <= 256)
+        return E == 4;
+    if (L == 512)
+        return E == 8;
+    return E == 8 || E == 16;
+}
+
+hipError_t launch_batched(const float2* specs, const int64_t* offsets, int nspec, int64_t cap,
+                          const float2* bank, int K, int M, int L, int E, float* planes,
                           int64_t* segpre, int grid, hipStream_t s)
 {
+    if (!batched_values_per_lane_ok(L, E))
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(segment_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, offsets, nspec,
-                       L - M, segpre);
+                       cap, L - M, segpre);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
     switch (L) {
-    case 256:  return launch_batched_L<256>(specs, offsets, nspec, bank, K, M, planes, segpre, grid, s);
-    case 512:  return launch_batched_L<512>(specs, offsets, nspec, bank, K, M, planes, segpre, grid, s);
-    case 1024: return launch_batched_L<1024>(specs, offsets, nspec, bank, K, M, planes, segpre, grid, s);
-    case 2048: return launch_batched_L<2048>(specs, offsets, nspec, bank, K, M, planes, segpre, grid, s);
-    case 4096: return launch_batched_L<4096>(specs, offsets, nspec, bank, K, M, planes, segpre, grid, s);
-    case 8192: return launch_batched_L<8192>(specs, offsets, nspec, bank, K, M, planes, segpre, grid, s);
+    case 256:  return launch_batched_L<256>(specs, offsets, nspec, cap, bank, K, M, E, planes, segpre, grid, s);
+    case 512:  return launch_batched_L<512>(specs, offsets, nspec, cap, bank, K, M, E, planes, segpre, grid, s);
+    case 1024: return launch_batched_L<1024>(specs, offsets, nspec, cap, bank, K, M, E, planes, segpre, grid, s);
+    case 2048: return launch_batched_L<2048>(specs, offsets, nspec, cap, bank, K, M, E, planes, segpre, grid, s);
+    case 4096: return launch_batched_L<4096>(specs, offsets, nspec, cap, bank, K, M, E, planes, segpre, grid, s);
+    case 8192: return launch_batched_L<8192>(specs, offsets, nspec, cap, bank, K, M, E, planes, segpre, grid, s);
     default:   return hipErrorInvalidValue;
     }
 }
@@ -883,7 +1084,100 @@ hipError_t launch_backward(const float2* spec, int64_t N, const float2* bank, in
         const int64_t chunk = nwin > 0 ? (nwin + tsplit - 1) / tsplit : 1;
         hipLaunchKernelGGL(reduce_grad_taps_kernel,
                            dim3((KM + kTapsCols - 1) / kTapsCols, (unsigned)tsplit),
-                           dim3(kTapsCols * kTapsRows), 0, s, partT, nwin, chunk, KM, tpart);
+                           dim3(kTapsCols * kTapsRows), 0, s, partT, nwin,
+                           (const int64_t*)nullptr, chunk, KM, tpart);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(reduce_grad_taps_final_kernel, dim3((KM + bs - 1) / bs), dim3(bs), 0,
+                           s, tpart, tsplit, KM, L, grad_taps);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+template <int L>
+static hipError_t launch_backward_batched_L(const float2* specs, const int64_t* offsets,
+                                            const int64_t* winpre, int nspec, int64_t cap,
+                                            const float2* bank, int K, int M, int zchunk,
+                                            int64_t maxwin, const float* dLdP, int want_A,
+                                            int want_T, float2* partA, float2* partT,
+                                            hipStream_t s)
+{
+    static std::atomic<int> cache[3][64];
+    const int nzc = (K + zchunk - 1) / zchunk;
+    int grid = 0;
+    hipError_t e = hipSuccess;
+    // persistent grid: the resident workgroups, or fewer if the bound on
+    // the items is smaller
+    if (want_T && M / 2 == Bwd<L>::T) {
+        if ((e = resident_grid(backward_batched_kernel<L, true, true>, Bwd<L>::T, cache[0], &grid)) != hipSuccess)
+            return e;
+    } else if (want_T) {
+        if ((e = resident_grid(backward_batched_kernel<L, true, false>, Bwd<L>::T, cache[1], &grid)) != hipSuccess)
+            return e;
+    } else {
+        if ((e = resident_grid(backward_batched_kernel<L, false, false>, Bwd<L>::T, cache[2], &grid)) != hipSuccess)
+            return e;
+    }
+    if ((int64_t)grid > maxwin * nzc)
+        grid = (int)(maxwin * nzc);
+    if (grid < 1)
+        return hipSuccess;
+    if (want_T && M / 2 == Bwd<L>::T)
+        hipLaunchKernelGGL((backward_batched_kernel<L, true, true>), dim3(grid), dim3(Bwd<L>::T), 0, s,
+                           specs, offsets, winpre, nspec, cap, bank, K, M, zchunk, maxwin, dLdP,
+                           want_A, partA, partT);
+    else if (want_T)
+        hipLaunchKernelGGL((backward_batched_kernel<L, true, false>), dim3(grid), dim3(Bwd<L>::T), 0,
+                           s, specs, offsets, winpre, nspec, cap, bank, K, M, zchunk, maxwin, dLdP,
+                           want_A, partA, partT);
+    else
+        hipLaunchKernelGGL((backward_batched_kernel<L, false, false>), dim3(grid), dim3(Bwd<L>::T), 0,
+                           s, specs, offsets, winpre, nspec, cap, bank, K, M, zchunk, maxwin, dLdP,
+                           want_A, partA, partT);
+    return hipGetLastError();
+}
+
+hipError_t launch_backward_batched(const float2* specs, const int64_t* offsets, int nspec,
+                                   int64_t cap, const float2* bank, int K, int M, int L,
+                                   const float* dLdP, float2* grad_specs, float2* grad_taps,
+                                   int zchunk, int64_t maxwin, int64_t* winpre, float2* partA,
+                                   float2* partT, int tsplit, double2* tpart, hipStream_t s)
+{
+    const int want_A = grad_specs != nullptr, want_T = grad_taps != nullptr;
+    hipLaunchKernelGGL(segment_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, offsets, nspec,
+                       cap, L - M, winpre);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    switch (L) {
+    case 256:  e = launch_backward_batched_L<256>(specs, offsets, winpre, nspec, cap, bank, K, M, zchunk, maxwin, dLdP, want_A, want_T, partA, partT, s); break;
+    case 512:  e = launch_backward_batched_L<512>(specs, offsets, winpre, nspec, cap, bank, K, M, zchunk, maxwin, dLdP, want_A, want_T, partA, partT, s); break;
+    case 1024: e = launch_backward_batched_L<1024>(specs, offsets, winpre, nspec, cap, bank, K, M, zchunk, maxwin, dLdP, want_A, want_T, partA, partT, s); break;
+    case 2048: e = launch_backward_batched_L<2048>(specs, offsets, winpre, nspec, cap, bank, K, M, zchunk, maxwin, dLdP, want_A, want_T, partA, partT, s); break;
+    case 4096: e = launch_backward_batched_L<4096>(specs, offsets, winpre, nspec, cap, bank, K, M, zchunk, maxwin, dLdP, want_A, want_T, partA, partT, s); break;
+    case 8192: e = launch_backward_batched_L<8192>(specs, offsets, winpre, nspec, cap, bank, K, M, zchunk, maxwin, dLdP, want_A, want_T, partA, partT, s); break;
+    default:   return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess)
+        return e;
+    const int bs = 256;
+    if (want_A && cap > 0) {
+        const int nzc = (K + zchunk - 1) / zchunk;
+        hipLaunchKernelGGL(reduce_grad_spec_batched_kernel, dim3((unsigned)((cap + bs - 1) / bs)),
+                           dim3(bs), 0, s, partA, offsets, winpre, nspec, cap, L, M, maxwin, nzc,
+                           grad_specs);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+    }
+    if (want_T) {
+        const int KM = K * M;
+        const int64_t chunk = maxwin > 0 ? (maxwin + tsplit - 1) / tsplit : 1;
+        hipLaunchKernelGGL(reduce_grad_taps_kernel,
+                           dim3((KM + kTapsCols - 1) / kTapsCols, (unsigned)tsplit),
+                           dim3(kTapsCols * kTapsRows), 0, s, partT, maxwin,
+                           (const int64_t*)(winpre + nspec), chunk, KM, tpart);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         hipLaunchKernelGGL(reduce_grad_taps_final_kernel, dim3((KM + bs - 1) / bs), dim3(bs), 0,

@@ -116,12 +116,38 @@ def test_validation_happens_before_any_device_call():
     assert L.fdas_correlate_ex(sp, 1000, bk, 85, 256, 2048, pl, -1, None) == _lib.FDAS_INVALID_ARG
     # batched and backward validation
     ws = _fake(0x4000)
-    assert L.fdas_correlate_batched(sp, _fake(0x5000), 0, None, 85, 256, 2048, None, None, 0, None) == _lib.FDAS_OK
-    assert L.fdas_correlate_batched(sp, _fake(0x5000), -1, bk, 85, 256, 2048, pl, ws, 1 << 20, None) == _lib.FDAS_INVALID_ARG
-    assert L.fdas_correlate_batched(sp, _fake(0x5000), 4, bk, 85, 256, 2048, pl, ws, 8, None) == _lib.FDAS_WORKSPACE_TOO_SMALL
-    assert L.fdas_correlate_batched(sp, _fake(0x5004), 4, bk, 85, 256, 2048, pl, ws, 1 << 20, None) == _lib.FDAS_INVALID_ARG
-    assert L.fdas_correlate_batched(sp, None, 4, bk, 85, 256, 2048, pl, ws, 1 << 20, None) == _lib.FDAS_INVALID_ARG
-    assert L.fdas_correlate_batched(sp, _fake(0x5000), 4, bk, 85, 256, 1000, pl, ws, 1 << 20, None) == _lib.FDAS_UNSUPPORTED
+    cap = 1 << 20
+    assert L.fdas_correlate_batched(sp, _fake(0x5000), 0, cap, None, 85, 256, 2048, None, None, 0, None) == _lib.FDAS_OK
+    assert L.fdas_correlate_batched(sp, _fake(0x5000), -1, cap, bk, 85, 256, 2048, pl, ws, 1 << 20, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_correlate_batched(sp, _fake(0x5000), 4, cap, bk, 85, 256, 2048, pl, ws, 8, None) == _lib.FDAS_WORKSPACE_TOO_SMALL
+    assert L.fdas_correlate_batched(sp, _fake(0x5004), 4, cap, bk, 85, 256, 2048, pl, ws, 1 << 20, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_correlate_batched(sp, None, 4, cap, bk, 85, 256, 2048, pl, ws, 1 << 20, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_correlate_batched(sp, _fake(0x5000), 4, cap, bk, 85, 256, 1000, pl, ws, 1 << 20, None) == _lib.FDAS_UNSUPPORTED
+    # capacity outside [0, 2^40]
+    assert L.fdas_correlate_batched(sp, _fake(0x5000), 4, -1, bk, 85, 256, 2048, pl, ws, 1 << 20, None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_correlate_batched(sp, _fake(0x5000), 4, (1 << 40) + 1, bk, 85, 256, 2048, pl, ws, 1 << 20, None) == _lib.FDAS_INVALID_ARG
+    # values per lane: 8 and 16 from L = 1024 on, else only the default
+    bx = L.fdas_correlate_batched_ex
+    assert bx(sp, _fake(0x5000), 4, cap, bk, 85, 256, 2048, pl, 4, 0, ws, 1 << 20, None) == _lib.FDAS_UNSUPPORTED
+    assert bx(sp, _fake(0x5000), 4, cap, bk, 85, 128, 512, pl, 16, 0, ws, 1 << 20, None) == _lib.FDAS_UNSUPPORTED
+    assert bx(sp, _fake(0x5000), 0, cap, bk, 85, 256, 2048, pl, 8, 0, ws, 1 << 20, None) == _lib.FDAS_OK
+    assert bx(sp, _fake(0x5000), 0, cap, bk, 85, 256, 8192, pl, 16, 0, ws, 1 << 20, None) == _lib.FDAS_OK
+    assert bx(sp, _fake(0x5000), 4, cap, bk, 85, 256, 2048, pl, 0, -1, ws, 1 << 20, None) == _lib.FDAS_INVALID_ARG
+    # batched adjoint: workspace by the gradients wanted, validation first
+    wb = L.fdas_backward_batched_workspace_bytes
+    both, only_s, only_t = wb(cap, 4, 9, 128, 2048, 0, 3), wb(cap, 4, 9, 128, 2048, 0, 1), wb(cap, 4, 9, 128, 2048, 0, 2)
+    assert both > max(only_s, only_t) > 0 and both % 256 == 0
+    assert wb(cap, 4, 9, 128, 2048, 0, 4) == 0 and wb(-1, 4, 9, 128, 2048, 0, 3) == 0
+    assert wb(cap, 4, 9, 2048, 2048, 0, 3) == 0 and wb(cap, 4, 9, 128, 2048, 10, 3) == 0
+    bb = L.fdas_correlate_backward_batched
+    assert bb(sp, _fake(0x5000), 4, cap, bk, 9, 128, 2048, pl, None, None, 0, ws, 0, None) == _lib.FDAS_OK
+    assert bb(sp, _fake(0x5000), 4, cap, bk, 9, 128, 2048, pl, sp, None, 0, ws, only_s - 256, None) == _lib.FDAS_WORKSPACE_TOO_SMALL
+    assert bb(sp, _fake(0x5000), 4, cap, bk, 9, 128, 2048, pl, sp, sp, 0, ws, only_s, None) == _lib.FDAS_WORKSPACE_TOO_SMALL
+    assert bb(sp, None, 4, cap, bk, 9, 128, 2048, pl, sp, None, 0, ws, both, None) == _lib.FDAS_INVALID_ARG
+    assert bb(sp, _fake(0x5000), 4, cap, bk, 9, 128, 2048, pl, sp, None, 0, _fake(0x4010), both, None) == _lib.FDAS_INVALID_ARG
+    assert bb(sp, _fake(0x5000), 4, cap, bk, 9, 128, 2048, pl, sp, None, 11, ws, both, None) == _lib.FDAS_INVALID_ARG
+    assert bb(sp, _fake(0x5000), -1, cap, bk, 9, 128, 2048, pl, sp, None, 0, ws, both, None) == _lib.FDAS_INVALID_ARG
+    assert bb(sp, _fake(0x5000), 4, cap, bk, 9, 128, 1000, pl, sp, None, 0, ws, both, None) == _lib.FDAS_UNSUPPORTED
     wsb = L.fdas_backward_workspace_bytes(4096, 9, 128, 2048, 0)
     assert wsb > 0 and wsb % 256 == 0
     assert L.fdas_backward_workspace_bytes(4096, 9, 2048, 2048, 0) == 0
@@ -149,17 +175,33 @@ def test_bank_elems():
 def test_autotune_validation_before_any_device_call():
     L = _lib.lib()
     p = _fake(0x10000)
-    Lo, go, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    out = _lib.Tuning()
     wsb = L.fdas_autotune_workspace_bytes(85, 4)
     assert wsb >= 86 * 8192 * 8
-    args = lambda ws, wsb_, K=85, M=256, n=4: (p, K, M, p, p, n, p, ws, wsb_, None,
-                                               ctypes.byref(Lo), ctypes.byref(go), ctypes.byref(ms))
+    args = lambda ws, wsb_, K=85, M=256, n=4, cap=1 << 20, flags=0: (
+        p, K, M, p, p, n, cap, p, ws, wsb_, flags, None, ctypes.byref(out))
     assert L.fdas_autotune_batched(*args(p, wsb - 1)) == _lib.FDAS_WORKSPACE_TOO_SMALL
     assert L.fdas_autotune_batched(*args(_fake(0x10010), wsb)) == _lib.FDAS_INVALID_ARG
     assert L.fdas_autotune_batched(*args(p, wsb, n=0)) == _lib.FDAS_INVALID_ARG
     assert L.fdas_autotune_batched(*args(p, wsb, M=255)) == _lib.FDAS_INVALID_ARG
-    assert L.fdas_autotune_batched(p, 85, 256, p, p, 4, p, p, wsb, None, None,
-                                   ctypes.byref(go), None) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_autotune_batched(*args(p, wsb, cap=0)) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_autotune_batched(*args(p, wsb, flags=4)) == _lib.FDAS_INVALID_ARG
+    assert L.fdas_autotune_batched(p, 85, 256, p, p, 4, 1 << 20, p, p, wsb, 0, None,
+                                   None) == _lib.FDAS_INVALID_ARG
+
+
+def test_autotune_candidates_cover_lengths_lanes_and_grids():
+    # every supported L from 512 with M <= L/2, both lane counts from 1024 on,
+    # grid factors 1 and 2
+    c = _lib.fdas_autotune_candidates(85, 256)
+    got = {(x["L"], x["E"], x["grid_factor"]) for x in c}
+    want = {(L, E, g) for L in (512, 1024, 2048, 4096, 8192)
+            for E in ((8,) if L == 512 else (16, 8)) for g in (1, 2)}
+    assert got == want and len(c) == len(want)
+    # wide templates rule out the short segments
+    assert {x["L"] for x in _lib.fdas_autotune_candidates(201, 512)} == {1024, 2048, 4096, 8192}
+    with pytest.raises(_lib.FdasError):
+        _lib.fdas_autotune_candidates(85, 255)
 
 
 def test_r2c_validation_before_any_device_call():

@@ -130,8 +130,9 @@ def test_emulated_batched_equals_plain(emu):
     ws = np.zeros(wsb, dtype=np.uint8)
     for grid in (0, 1, 5, 13):
         planes[:] = np.nan
-        assert emu.fdas_correlate_batched_ex(_p(packed), _p(offs), len(lens), _p(bank), K, M, L,
-                                             _p(planes), grid, _p(ws), ctypes.c_size_t(wsb),
+        assert emu.fdas_correlate_batched_ex(_p(packed), _p(offs), len(lens),
+                                             ctypes.c_int64(int(offs[-1])), _p(bank), K, M, L,
+                                             _p(planes), 0, grid, _p(ws), ctypes.c_size_t(wsb),
                                              None) == 0
         _check_guards(buf, planes)
         for b, n in enumerate(lens):
@@ -143,6 +144,133 @@ def test_emulated_batched_equals_plain(emu):
                                       _p(one), None) == 0
             assert np.array_equal(view, one), b
             assert _rel(view, native.power(specs[b], taps)) < TOL
+
+
+@pytest.mark.parametrize("L,E", [(1024, 8), (2048, 8), (1024, 16), (8192, 8), (4096, 8)])
+def test_emulated_batched_values_per_lane(emu, L, E):
+    # the other lane geometry of the batched kernel: same plane up to FP32
+    # rounding, every element written, nothing outside the buffer
+    M, K = 256, 3
+    lens = [1900, 1, 770, 0, 2600]
+    taps = syn.random_taps(L + E, K, M)
+    bank = _bank(emu, taps, L)
+    specs = [syn.random_spectrum(40 + i, n) for i, n in enumerate(lens)]
+    packed = np.concatenate(specs).astype(np.complex64)
+    offs = np.zeros(len(lens) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(lens)
+    buf, planes = _guarded((K * offs[-1],))
+    emu.fdas_batched_workspace_bytes.restype = ctypes.c_size_t
+    wsb = emu.fdas_batched_workspace_bytes(len(lens))
+    ws = np.zeros(wsb, dtype=np.uint8)
+    assert emu.fdas_correlate_batched_ex(_p(packed), _p(offs), len(lens),
+                                         ctypes.c_int64(int(offs[-1])), _p(bank), K, M, L,
+                                         _p(planes), E, 0, _p(ws), ctypes.c_size_t(wsb),
+                                         None) == 0
+    _check_guards(buf, planes)
+    for b, n in enumerate(lens):
+        if n:
+            view = planes[K * offs[b]:K * offs[b + 1]].reshape(K, n)
+            assert _rel(view, native.power(specs[b], taps)) < TOL, b
+
+
+def test_emulated_batched_offsets_clamped_to_capacity(emu):
+    # offsets the device reads past the caller's capacity: the spectra are
+    # cut at the capacity, nothing is written beyond K * capacity floats
+    L, M, K = 512, 64, 2
+    lens = [300, 500]
+    taps = syn.random_taps(3, K, M)
+    bank = _bank(emu, taps, L)
+    packed = syn.random_spectrum(4, sum(lens))
+    cap = 600
+    offs = np.array([0, 300, 5000], dtype=np.int64)
+    buf, planes = _guarded((K * cap,))
+    wsb = emu.fdas_batched_workspace_bytes(2)
+    ws = np.zeros(wsb, dtype=np.uint8)
+    assert emu.fdas_correlate_batched_ex(_p(packed), _p(offs), 2, ctypes.c_int64(cap), _p(bank),
+                                         K, M, L, _p(planes), 0, 0, _p(ws),
+                                         ctypes.c_size_t(wsb), None) == 0
+    _check_guards(buf, planes)
+    second = planes[K * 300:K * 600].reshape(K, 300)
+    assert _rel(second, native.power(packed[300:600], taps)) < TOL
+
+
+@pytest.mark.parametrize("L,M,zchunk", [(512, 128, 2), (256, 32, 1), (1024, 64, 3), (512, 64, 0)])
+def test_emulated_backward_batched(emu, L, M, zchunk):
+    # the batched adjoint: each spectrum's gradient bitwise the single-spectrum
+    # call's with the same template chunking, the taps gradient the batch sum,
+    # both against the oracle; empty and one-bin spectra included
+    K = 3
+    lens = [700, 0, 1, 2 * (L - M) + 5, 97]
+    taps = syn.random_taps(L + M, K, M)
+    bank = _bank(emu, taps, L)
+    specs = [syn.random_spectrum(60 + i, n) for i, n in enumerate(lens)]
+    packed = np.concatenate(specs).astype(np.complex64)
+    offs = np.zeros(len(lens) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(lens)
+    tot = int(offs[-1])
+    rng = np.random.default_rng(L + M)
+    ws_ = [rng.random((K, n), dtype=np.float32) for n in lens]
+    wpk = np.concatenate([w.reshape(-1) for w in ws_]).astype(np.float32)
+    emu.fdas_backward_batched_workspace_bytes.restype = ctypes.c_size_t
+    wsb = emu.fdas_backward_batched_workspace_bytes(ctypes.c_int64(tot), len(lens), K, M, L,
+                                                    zchunk, 3)
+    ws = np.zeros(wsb + 256, dtype=np.uint8)
+    wsp = ctypes.c_void_p((ws.ctypes.data + 255) & ~255)
+    gbuf, gA = _guarded((2 * tot,))            # complex64 as float pairs
+    gT = np.full((K, M), np.nan, dtype=np.complex64)
+    assert emu.fdas_correlate_backward_batched(_p(packed), _p(offs), len(lens),
+                                               ctypes.c_int64(tot), _p(bank), K, M, L, _p(wpk),
+                                               _p(gA), _p(gT), zchunk, wsp, ctypes.c_size_t(wsb),
+                                               None) == 0
+    _check_guards(gbuf, gA)
+    gA = gA.view(np.complex64)
+    emu.fdas_backward_workspace_bytes.restype = ctypes.c_size_t
+    sumT = np.zeros((K, M), dtype=np.complex128)
+    for b, n in enumerate(lens):
+        if n == 0:
+            continue
+        # the batch's default chunking is the single call's only when given
+        zc = zchunk if zchunk else K
+        w1 = emu.fdas_backward_workspace_bytes(ctypes.c_int64(n), K, M, L, zc)
+        ws1 = np.zeros(w1 + 256, dtype=np.uint8)
+        p1 = ctypes.c_void_p((ws1.ctypes.data + 255) & ~255)
+        a1 = np.full(n, np.nan, dtype=np.complex64)
+        t1 = np.full((K, M), np.nan, dtype=np.complex64)
+        assert emu.fdas_correlate_backward_ex(_p(specs[b]), ctypes.c_int64(n), _p(bank), K, M, L,
+                                              _p(ws_[b]), _p(a1), _p(t1), zc, p1,
+                                              ctypes.c_size_t(w1), None) == 0
+        if zchunk:
+            assert np.array_equal(gA[offs[b]:offs[b + 1]], a1), b
+        rA, rT = native.grads(specs[b], taps, ws_[b])
+        assert _rel(gA[offs[b]:offs[b + 1]], rA) < TOL, b
+        sumT += rT
+    assert _rel(gT, sumT) < TOL
+    # spectra gradient alone: same values
+    gA2 = np.full(tot, np.nan, dtype=np.complex64)
+    assert emu.fdas_correlate_backward_batched(_p(packed), _p(offs), len(lens),
+                                               ctypes.c_int64(tot), _p(bank), K, M, L, _p(wpk),
+                                               _p(gA2), None, zchunk, wsp, ctypes.c_size_t(wsb),
+                                               None) == 0
+    assert np.allclose(gA2, gA, rtol=0, atol=1e-6 * np.max(np.abs(gA)))
+
+
+def test_emulated_backward_batched_empty_batch(emu):
+    # no spectra: zero gradients, every output written
+    K, M, L, cap = 2, 64, 512, 50
+    taps = syn.random_taps(1, K, M)
+    bank = _bank(emu, taps, L)
+    offs = np.zeros(1, dtype=np.int64)
+    wsb = emu.fdas_backward_batched_workspace_bytes(ctypes.c_int64(cap), 0, K, M, L, 0, 3)
+    ws = np.zeros(wsb + 256, dtype=np.uint8)
+    wsp = ctypes.c_void_p((ws.ctypes.data + 255) & ~255)
+    spec = np.zeros(cap, dtype=np.complex64)
+    w = np.zeros(K * cap, dtype=np.float32)
+    gA = np.full(cap, np.nan, dtype=np.complex64)
+    gT = np.full((K, M), np.nan, dtype=np.complex64)
+    assert emu.fdas_correlate_backward_batched(_p(spec), _p(offs), 0, ctypes.c_int64(cap),
+                                               _p(bank), K, M, L, _p(w), _p(gA), _p(gT), 0, wsp,
+                                               ctypes.c_size_t(wsb), None) == 0
+    assert np.all(gA == 0) and np.all(gT == 0)
 
 
 # (256, 32, 29131): 131 windows, so the taps-gradient reduction runs in two

@@ -152,23 +152,92 @@ def test_workload3_full_sampled(fd):
     assert bool(torch.isfinite(planes).all())
 
 
-def test_autotuner_picks_a_valid_segment_length(fd):
-    w = syn.workload(3, nspec=10, length_scale=1 / 16)
+def _tune_batch(fd, nspec, scale):
+    w = syn.workload(3, nspec=nspec, length_scale=scale)
     K, M = w.K, w.M
     taps = torch.from_numpy(fd.fdas_make_templates_host(w.zmax, w.dz, M)).cuda()
     packed, o = w.packed()
     specs = torch.from_numpy(packed).cuda()
     offs = torch.from_numpy(o).cuda()
     planes = torch.empty(K * int(o[-1]), dtype=torch.float32, device="cuda")
-    ws = torch.empty(fd._lib.fdas_autotune_workspace_bytes(K, len(w.spectra)),
-                     dtype=torch.uint8, device="cuda")
-    L, grid, ms = fd._lib.fdas_autotune_batched(taps, K, M, specs, offs, len(w.spectra), planes, ws)
-    assert L in (512, 1024, 2048, 4096, 8192) and M <= L // 2 and grid == 0 and ms > 0
-    # cached: the same answer without re-timing
-    assert fd._lib.fdas_autotune_batched(taps, K, M, specs, offs, len(w.spectra), planes, ws)[0] == L
-    bank = fd.prepare_bank(taps, L)
-    planes = fd.correlate_batched(specs, offs, bank, K, M, L)
-    for b in (0, 9):
+    ws = torch.empty(fd._lib.fdas_autotune_workspace_bytes(K, nspec), dtype=torch.uint8,
+                     device="cuda")
+    return w, K, M, taps, specs, offs, o, planes, ws
+
+
+def test_autotuner_within_3_percent_of_exhaustive_sweep(fd):
+    # a small batch (32 spectra of ~2^15..2^18 bins); the tuner's choice
+    # (timed afresh, caches bypassed) against an exhaustive sweep of the same
+    # candidates, each timed in three interleaved rounds (best round counts)
+    w, K, M, taps, specs, offs, o, planes, ws = _tune_batch(fd, 32, 1 / 8)
+    nspec = len(w.spectra)
+    t = fd._lib.fdas_autotune_batched(taps, K, M, specs, offs, nspec, planes, ws,
+                                      flags=fd._lib.TUNE_NO_CACHE)
+    assert t["from_cache"] == 0 and t["ms"] > 0 and M <= t["L"] // 2
+    cands = fd._lib.fdas_autotune_candidates(K, M)
+    assert (t["L"], t["E"], t["grid_factor"]) in {(c["L"], c["E"], c["grid_factor"]) for c in cands}
+    banks = {L: fd.prepare_bank(taps, L) for L in {c["L"] for c in cands}}
+    bws = torch.empty(fd.fdas_batched_workspace_bytes(nspec), dtype=torch.uint8, device="cuda")
+    best = {}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for _ in range(3):
+        for c in cands:
+            grid = 0 if c["grid_factor"] == 1 else \
+                c["grid_factor"] * fd._lib.fdas_batched_resident_grid(c["L"], c["E"], M)
+
+            def run():
+                fd.fdas_correlate_batched_ex(specs, offs, nspec, banks[c["L"]], K, M, c["L"],
+                                             planes, c["E"], grid, bws)
+            run()
+            ev[0].record()
+            for _ in range(3):
+                run()
+            ev[1].record()
+            torch.cuda.synchronize()
+            key = (c["L"], c["E"], c["grid_factor"])
+            best[key] = min(best.get(key, 1e30), ev[0].elapsed_time(ev[1]) / 3)
+    fastest = min(best.values())
+    chosen = best[(t["L"], t["E"], t["grid_factor"])]
+    assert chosen <= 1.03 * fastest, (t, chosen, fastest, best)
+    # the tuned shape gives the plain path's plane at that segment length
+    bank = banks[t["L"]]
+    fd.fdas_correlate_batched_ex(specs, offs, nspec, bank, K, M, t["L"], planes, t["E"], t["grid"],
+                                 bws)
+    for b in (0, nspec - 1):
         n = int(o[b + 1] - o[b])
-        ref = fd.correlate(specs[o[b]:o[b + 1]], bank, K, M, L)
-        assert torch.equal(planes[K * o[b]:K * o[b + 1]].view(K, n), ref)
+        got = planes[K * o[b]:K * o[b + 1]].view(K, n)
+        if t["E"] == 0 or t["E"] == (16 if t["L"] >= 1024 else (8 if t["L"] == 512 else 4)):
+            assert torch.equal(got, fd.correlate(specs[o[b]:o[b + 1]], bank, K, M, t["L"]))
+        ref = native.power(w.spectra[b], ot.templates(w.zmax, w.dz, M))
+        assert np.max(np.abs(got.cpu().numpy() - ref)) / np.max(ref) < TOL
+
+
+def test_autotuner_cache_file(fd, tmp_path, monkeypatch):
+    # the choice persists in a JSON file: written after timing, returned from
+    # the process cache on the next call, and a hand-written entry for a key
+    # this process has not tuned is read from the file without timing
+    import json
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("FDAS_TUNE_CACHE", str(path))
+    w, K, M, taps, specs, offs, o, planes, ws = _tune_batch(fd, 6, 1 / 64)
+    nspec = len(w.spectra)
+    t = fd._lib.fdas_autotune_batched(taps, K, M, specs, offs, nspec, planes, ws,
+                                      flags=fd._lib.TUNE_REFRESH)
+    assert t["from_cache"] == 0
+    data = json.loads(path.read_text())
+    props = torch.cuda.get_device_properties(0)
+    key = [k for k in data if f"|K{K}|M{M}|" in k]
+    assert len(key) == 1 and key[0].startswith(props.gcnArchName)
+    assert data[key[0]]["L"] == t["L"] and data[key[0]]["E"] == t["E"]
+    t2 = fd._lib.fdas_autotune_batched(taps, K, M, specs, offs, nspec, planes, ws)
+    assert t2["from_cache"] == 1 and (t2["L"], t2["E"], t2["grid"]) == (t["L"], t["E"], t["grid"])
+    # a key with other taps (M = 128): planted in the file by hand
+    M2 = 128
+    taps2 = torch.from_numpy(fd.fdas_make_templates_host(w.zmax, w.dz, M2)).cuda()
+    planted = key[0].replace(f"|M{M}|", f"|M{M2}|")
+    data[planted] = {"L": 1024, "E": 8, "grid_factor": 2, "ms": 1.5}
+    path.write_text("{\n" + ",\n".join(f'"{k}": ' + json.dumps(v) for k, v in data.items())
+                    + "\n}\n")
+    t3 = fd._lib.fdas_autotune_batched(taps2, K, M2, specs, offs, nspec, planes, ws)
+    assert t3["from_cache"] == 1 and (t3["L"], t3["E"], t3["grid_factor"]) == (1024, 8, 2)
+    assert t3["grid"] == 2 * fd._lib.fdas_batched_resident_grid(1024, 8, M2) and t3["ms"] == 1.5
