@@ -335,10 +335,12 @@ size_t fdas_backward_batched_workspace_bytes(int64_t capacity, int nspec, int K,
  * Adjoint of fdas_correlate_batched for Lw = sum_b sum_{z,r} w_b[z][r]
  * P_b[z][r] (not in the paper; the single-spectrum adjoint of
  * fdas_correlate_backward applied to every spectrum of the batch), in one
- * persistent launch of a fixed grid over the (window, template chunk) items
- * of all spectra, plus a scan and the FP64 reductions; offsets are read on
- * the device, so the call makes no host wait, allocation or memset (for
- * nspec >= 1) and can be captured in a graph.
+ * launch of a grid fixed by the host's bound on the window count (one
+ * workgroup per (window, template chunk) item of all spectra; those past the
+ * batch's actual windows exit at once), plus a scan and the FP64
+ * reductions; offsets are read on the device, so the call makes no host
+ * wait, allocation or memset (for nspec >= 1) and can be captured in a
+ * graph.
  *   specs_dev, offsets_dev, nspec, capacity : as fdas_correlate_batched
  *                   (offsets clamped to [0, capacity]);
  *   bank_dev      : prepared bank for (K, M, L);

@@ -697,11 +697,15 @@ __global__ void reduce_grad_taps_final_kernel(const double2* __restrict__ tpart,
 // batched_kernel, dL/dP packed like the planes).  A window of spectrum b is
 // the same window as in the single-spectrum adjoint; windows of all spectra
 // are numbered globally by the scan winpre (windows per spectrum =
-// ceil(N_b / B), the segment count), and the persistent kernel walks the
-// flattened (window, template chunk) items in a grid-stride loop, so the grid
-// is fixed whatever the batch.  Items past maxwin (the host's bound on the
-// window count, which only offsets that overlap could exceed) are skipped, so
-// no partial buffer is overrun.
+// ceil(N_b / B), the segment count).  The grid is fixed by the host's bound
+// maxwin on the window count (which only offsets that overlap could exceed)
+// times the template chunks, so one launch covers any batch within the
+// bound and a captured graph serves new batches.  Workgroups past the
+// batch's actual window count exit at once, so no partial buffer is overrun.
+// One window per workgroup (global window blockIdx.z * gridDim.x +
+// blockIdx.x), as in the single-spectrum kernel, so the body allocates the
+// same registers (a grid-stride loop over windows made the compiler keep
+// more values live and spill).
 template <int L, bool WANT_T, bool EDGE>
 __global__ __launch_bounds__(Bwd<L>::T, WANT_T ? BwdGeometry<L>::kMinWaves
                                                : BwdGeometry<L>::kMinWavesSpec) void
@@ -713,31 +717,27 @@ backward_batched_kernel(const float2* __restrict__ specs, const int64_t* __restr
 {
     using Bk = Bwd<L>;
     __shared__ float2 lds[2][LdsSize<L>::value];
-    const int nzc = (K + zchunk - 1) / zchunk;
     const int64_t nw = min(winpre[nspec], maxwin);
-    const int64_t items = nw * nzc;
-    if ((int64_t)blockIdx.x >= items)
+    const int c = blockIdx.y;
+    const int z0 = c * zchunk;
+    const int z1 = min(K, z0 + zchunk);
+    const int64_t g = (int64_t)blockIdx.z * gridDim.x + blockIdx.x;
+    if (g >= nw)
         return;     // uniform across the workgroup, before any barrier
     const int t = threadIdx.x;
     float2 tw[Bk::NTW];
     Bk::F::twiddles(tw, bank + (int64_t)K * L, t);
     float2* la = lds[0];
     float2* lb = lds[1];
-    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
-        const int64_t g = it / nzc;
-        const int c = (int)(it - g * nzc);
-        const int b = owner(winpre, nspec, g);
-        int64_t off, Nb;
-        spec_range(offsets, b, cap, off, Nb);
-        const int z0 = c * zchunk;
-        const int z1 = min(K, z0 + zchunk);
-        float2 H[Bk::E];
-        Bk::W::load_row(H, bank, z0, t);
-        Bk::template item<WANT_T, EDGE>(specs + off, Nb, bank, M, g - winpre[b], z0, z1,
-                                        dLdP + (int64_t)K * off, want_A != 0,
-                                        partA + ((int64_t)c * maxwin + g) * L,
-                                        partT + g * (int64_t)K * M, tw, la, lb, t, H);
-    }
+    const int b = owner(winpre, nspec, g);
+    int64_t off, Nb;
+    spec_range(offsets, b, cap, off, Nb);
+    float2 H[Bk::E];
+    Bk::W::load_row(H, bank, z0, t);
+    Bk::template item<WANT_T, EDGE>(specs + off, Nb, bank, M, g - winpre[b], z0, z1,
+                                    dLdP + (int64_t)K * off, want_A != 0,
+                                    partA + ((int64_t)c * maxwin + g) * L,
+                                    partT + g * (int64_t)K * M, tw, la, lb, t, H);
 }
 
 // grad[k] for every packed bin k < cap: the bins of spectrum b (the last b
@@ -1096,6 +1096,8 @@ hipError_t launch_backward(const float2* spec, int64_t N, const float2* bank, in
     return hipSuccess;
 }
 
+constexpr int64_t kMaxBwdGridX = int64_t(1) << 22;
+
 template <int L>
 static hipError_t launch_backward_batched_L(const float2* specs, const int64_t* offsets,
                                             const int64_t* winpre, int nspec, int64_t cap,
@@ -1104,36 +1106,22 @@ static hipError_t launch_backward_batched_L(const float2* specs, const int64_t* 
                                             int want_T, float2* partA, float2* partT,
                                             hipStream_t s)
 {
-    static std::atomic<int> cache[3][64];
     const int nzc = (K + zchunk - 1) / zchunk;
-    int grid = 0;
-    hipError_t e = hipSuccess;
-    // persistent grid: the resident workgroups, or fewer if the bound on
-    // the items is smaller
-    if (want_T && M / 2 == Bwd<L>::T) {
-        if ((e = resident_grid(backward_batched_kernel<L, true, true>, Bwd<L>::T, cache[0], &grid)) != hipSuccess)
-            return e;
-    } else if (want_T) {
-        if ((e = resident_grid(backward_batched_kernel<L, true, false>, Bwd<L>::T, cache[1], &grid)) != hipSuccess)
-            return e;
-    } else {
-        if ((e = resident_grid(backward_batched_kernel<L, false, false>, Bwd<L>::T, cache[2], &grid)) != hipSuccess)
-            return e;
-    }
-    if ((int64_t)grid > maxwin * nzc)
-        grid = (int)(maxwin * nzc);
-    if (grid < 1)
+    // one workgroup per (window, chunk): windows x + gridDim.x * z
+    const int64_t gx = maxwin < kMaxBwdGridX ? maxwin : kMaxBwdGridX;
+    const dim3 grid((unsigned)gx, (unsigned)nzc, (unsigned)((maxwin + gx - 1) / (gx > 0 ? gx : 1)));
+    if (maxwin < 1)
         return hipSuccess;
     if (want_T && M / 2 == Bwd<L>::T)
-        hipLaunchKernelGGL((backward_batched_kernel<L, true, true>), dim3(grid), dim3(Bwd<L>::T), 0, s,
+        hipLaunchKernelGGL((backward_batched_kernel<L, true, true>), grid, dim3(Bwd<L>::T), 0, s,
                            specs, offsets, winpre, nspec, cap, bank, K, M, zchunk, maxwin, dLdP,
                            want_A, partA, partT);
     else if (want_T)
-        hipLaunchKernelGGL((backward_batched_kernel<L, true, false>), dim3(grid), dim3(Bwd<L>::T), 0,
+        hipLaunchKernelGGL((backward_batched_kernel<L, true, false>), grid, dim3(Bwd<L>::T), 0,
                            s, specs, offsets, winpre, nspec, cap, bank, K, M, zchunk, maxwin, dLdP,
                            want_A, partA, partT);
     else
-        hipLaunchKernelGGL((backward_batched_kernel<L, false, false>), dim3(grid), dim3(Bwd<L>::T), 0,
+        hipLaunchKernelGGL((backward_batched_kernel<L, false, false>), grid, dim3(Bwd<L>::T), 0,
                            s, specs, offsets, winpre, nspec, cap, bank, K, M, zchunk, maxwin, dLdP,
                            want_A, partA, partT);
     return hipGetLastError();
