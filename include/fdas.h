@@ -277,6 +277,28 @@ int fdas_correlate_batched_ex(const fdas_cf32 *specs_dev, const int64_t *offsets
                               int M, int L, float *planes_dev, int E, int grid, void *ws_dev,
                               size_t ws_bytes, hipStream_t stream);
 
+/*
+ * Allocation-free form of fdas_correlate_batched, for callers that cannot
+ * allocate device memory: code under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, results (bitwise) and
+ * launches as fdas_correlate_batched at the default launch shape, without
+ * ws_dev / ws_bytes: the per-spectrum segment prefix sums (nspec + 1 int64)
+ * live in a fixed device array inside the library, one per GPU, of
+ * FDAS_NOALLOC_MAX_SPECTRA + 1 entries (512 KB), held from the first call on
+ * that GPU until the process ends.  nspec above FDAS_NOALLOC_MAX_SPECTRA is
+ * rejected with FDAS_INVALID_ARG before anything is launched.  The call
+ * makes no hipMalloc, hipFree or other allocating call; its first call on a
+ * device looks up the array's device address (hipGetSymbolAddress).  Every
+ * call on a GPU shares that GPU's array, and the scan rewrites every entry a
+ * call reads, so no state carries over between calls; calls that overlap in
+ * time on one GPU (other streams, other threads) race on it and must be
+ * serialised by the caller.
+ */
+#define FDAS_NOALLOC_MAX_SPECTRA 65536
+int fdas_correlate_batched_noalloc(const fdas_cf32 *specs_dev, const int64_t *offsets_dev,
+                                   int nspec, int64_t capacity, const fdas_cf32 *bank_dev, int K,
+                                   int M, int L, float *planes_dev, hipStream_t stream);
+
 /* Bytes of device workspace for fdas_correlate_backward(_ex) with the same
  * (N, K, M, L, zchunk; 0 = default), a multiple of 256; 0 for an invalid
  * geometry.  Holds the per-window partial gradients,

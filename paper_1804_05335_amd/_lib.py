@@ -44,6 +44,7 @@ SIGNATURES = [
     ("fdas_correlate_batched", _I, [_P, _P, _I, _I64, _P, _I, _I, _I, _P, _P, _SZ, _P]),
     ("fdas_correlate_batched_ex", _I, [_P, _P, _I, _I64, _P, _I, _I, _I, _P, _I, _I, _P, _SZ,
                                        _P]),
+    ("fdas_correlate_batched_noalloc", _I, [_P, _P, _I, _I64, _P, _I, _I, _I, _P, _P]),
     ("fdas_autotune_workspace_bytes", _SZ, [_I, _I]),
     ("fdas_autotune_candidates", _I, [_I, _I, _P, _I, ctypes.POINTER(_I)]),
     ("fdas_batched_resident_grid", _I, [_I, _I, _I, ctypes.POINTER(_I)]),
@@ -259,6 +260,25 @@ def fdas_correlate_batched_ex(specs, offsets, nspec: int, bank, K: int, M: int, 
                                            L, _ptr(planes), E, grid, _ptr(ws), ws.numel(),
                                            _stream(stream, specs)),
            "fdas_correlate_batched")
+
+
+# most spectra fdas_correlate_batched_noalloc takes (its fixed device array)
+NOALLOC_MAX_SPECTRA = 65536
+
+
+def fdas_correlate_batched_noalloc(specs, offsets, nspec: int, bank, K: int, M: int, L: int,
+                                   planes, stream=None) -> None:
+    """fdas_correlate_batched without a workspace (the library's fixed device
+    array holds the segment prefix): for callers that cannot allocate."""
+    import torch
+    _require(specs, torch.complex64, "specs")
+    _require(offsets, torch.int64, "offsets", nspec + 1)
+    _require(bank, torch.complex64, "bank", fdas_bank_elems(K, L))
+    _require(planes, torch.float32, "planes")
+    _check(lib().fdas_correlate_batched_noalloc(_ptr(specs), _ptr(offsets), nspec,
+                                                batched_capacity(specs, planes, K), _ptr(bank),
+                                                K, M, L, _ptr(planes), _stream(stream, specs)),
+           "fdas_correlate_batched_noalloc")
 
 
 def fdas_backward_workspace_bytes(N: int, K: int, M: int, L: int, zchunk: int = 0) -> int:

@@ -472,6 +472,40 @@ int fdas_correlate_batched(const fdas_cf32* specs_dev, const int64_t* offsets_de
                                      planes_dev, 0, 0, ws_dev, ws_bytes, stream);
 }
 
+int fdas_correlate_batched_noalloc(const fdas_cf32* specs_dev, const int64_t* offsets_dev,
+                                   int nspec, int64_t capacity, const fdas_cf32* bank_dev, int K,
+                                   int M, int L, float* planes_dev, hipStream_t stream)
+{
+    int st = check_geometry(K, M, L);
+    if (st)
+        return st;
+    if (nspec < 0 || nspec > FDAS_NOALLOC_MAX_SPECTRA)
+        return fail(FDAS_INVALID_ARG,
+                    "nspec = %d outside [0, %d], the allocation-free call's fixed maximum "
+                    "(use fdas_correlate_batched with a workspace for more)",
+                    nspec, FDAS_NOALLOC_MAX_SPECTRA);
+    if (capacity < 0 || capacity > kMaxCapacity)
+        return fail(FDAS_INVALID_ARG, "capacity = %lld outside [0, 2^40]", (long long)capacity);
+    if (nspec == 0)
+        return ok();
+    if (!specs_dev || !offsets_dev || !bank_dev || !planes_dev)
+        return fail(FDAS_INVALID_ARG, "specs, offsets, bank and planes must not be NULL");
+    if (!aligned(specs_dev, 8) || !aligned(offsets_dev, 8) || !aligned(bank_dev, 16) ||
+        !aligned(planes_dev, 4))
+        return fail(FDAS_INVALID_ARG,
+                    "misaligned pointer (specs 8 B, offsets 8 B, bank 16 B, planes 4 B)");
+    int64_t* segpre = nullptr;
+    hipError_t e = fdas::noalloc_segpre(&segpre);
+    if (e != hipSuccess)
+        return hip_fail(e, "allocation-free batched call: device scratch lookup");
+    e = fdas::launch_batched(reinterpret_cast<const float2*>(specs_dev), offsets_dev, nspec,
+                             capacity, reinterpret_cast<const float2*>(bank_dev), K, M, L, 0,
+                             planes_dev, segpre, 0, stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "allocation-free batched launch");
+    return ok();
+}
+
 namespace {
 
 int backward_zchunk(int64_t nwin, int K, int zchunk)

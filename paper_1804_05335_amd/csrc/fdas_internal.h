@@ -45,6 +45,11 @@ hipError_t launch_batched(const float2* specs, const int64_t* offsets, int nspec
                           const float2* bank, int K, int M, int L, int E, float* planes,
                           int64_t* segpre, int grid, hipStream_t s);
 
+// Device address of this device's segment-prefix array for the
+// allocation-free batched call (FDAS_NOALLOC_MAX_SPECTRA + 1 int64, a
+// file-scope device array; looked up on the first call on each device).
+hipError_t noalloc_segpre(int64_t** out);
+
 // Adjoint: window kernel into partA [nzc][nwin][L] / partT [nwin][K][M], then
 // the FP64 reductions into grad_spec [N] / grad_taps [K][M] (either may be
 // null); the taps reduction sums tsplit window chunks into tpart

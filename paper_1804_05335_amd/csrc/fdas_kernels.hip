@@ -1004,6 +1004,45 @@ bool batched_values_per_lane_ok(int L, int E)
     return E == 8 || E == 16;
 }
 
+// ---- allocation-free batched correlation -------------------------------------
+//
+// fdas_correlate_batched_noalloc keeps the segment prefix segpre[nspec + 1]
+// in this file-scope device array instead of a caller workspace.  Every GPU
+// the library runs on holds its own copy until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in symbol): the device address is looked up once per device with
+// hipGetSymbolAddress and kept in g_noalloc_ptr.  The scan kernel writes
+// every entry the correlation kernel reads (segpre[0] = 0 and segpre[1..nspec]),
+// so nothing has to be cleared between calls; calls that overlap on one GPU
+// share the array and race.
+static __device__ __align__(256) int64_t scratch[FDAS_NOALLOC_MAX_SPECTRA + 1];
+
+constexpr int kMaxDevices = 64;
+static std::atomic<int64_t*> g_noalloc_ptr[kMaxDevices];
+
+hipError_t noalloc_segpre(int64_t** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    int64_t* p = g_noalloc_ptr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        void* addr = nullptr;
+        e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        if (!addr)
+            return hipErrorInvalidSymbol;
+        p = static_cast<int64_t*>(addr);
+        g_noalloc_ptr[dev].store(p, std::memory_order_release);
+    }
+    *out = p;
+    return hipSuccess;
+}
+
 hipError_t launch_batched(const float2* specs, const int64_t* offsets, int nspec, int64_t cap,
                           const float2* bank, int K, int M, int L, int E, float* planes,
                           int64_t* segpre, int grid, hipStream_t s)

@@ -21,6 +21,7 @@
 #define __launch_bounds__(...)
 #define __shared__ static
 #define __restrict__
+#define __align__(n) __attribute__((aligned(n)))
 #define __builtin_nontemporal_store(v, p) (*(p) = (v))
 
 struct float2 { float x, y; };
@@ -113,7 +114,15 @@ inline unsigned atomicAdd(unsigned* p, unsigned v) { return __atomic_fetch_add(p
 inline void sincospi(double x, double* s, double* c) { *s = std::sin(M_PI * x); *c = std::cos(M_PI * x); }
 
 typedef int hipError_t;
-enum { hipSuccess = 0, hipErrorInvalidValue = 1 };
+enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorInvalidDevice = 101,
+       hipErrorInvalidSymbol = 13 };
+// a device symbol is a host object here: its address is the device address
+#define HIP_SYMBOL(x) (&(x))
+inline hipError_t hipGetSymbolAddress(void** p, const void* sym)
+{
+    *p = const_cast<void*>(sym);
+    return hipSuccess;
+}
 enum hipMemcpyKind { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2 };
 typedef struct ihipStream_t* hipStream_t;
 enum { hipDeviceAttributeMultiprocessorCount = 0 };

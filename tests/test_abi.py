@@ -133,6 +133,17 @@ def test_validation_happens_before_any_device_call():
     assert bx(sp, _fake(0x5000), 0, cap, bk, 85, 256, 2048, pl, 8, 0, ws, 1 << 20, None) == _lib.FDAS_OK
     assert bx(sp, _fake(0x5000), 0, cap, bk, 85, 256, 8192, pl, 16, 0, ws, 1 << 20, None) == _lib.FDAS_OK
     assert bx(sp, _fake(0x5000), 4, cap, bk, 85, 256, 2048, pl, 0, -1, ws, 1 << 20, None) == _lib.FDAS_INVALID_ARG
+    # allocation-free batched call: the fixed maximum batch and the usual checks, before any launch
+    na = L.fdas_correlate_batched_noalloc
+    assert na(sp, _fake(0x5000), 0, cap, None, 85, 256, 2048, None, None) == _lib.FDAS_OK
+    assert na(sp, _fake(0x5000), 65537, cap, bk, 85, 256, 2048, pl, None) == _lib.FDAS_INVALID_ARG
+    assert b"allocation-free" in L.fdas_last_error()
+    assert na(sp, _fake(0x5000), -1, cap, bk, 85, 256, 2048, pl, None) == _lib.FDAS_INVALID_ARG
+    assert na(sp, _fake(0x5004), 4, cap, bk, 85, 256, 2048, pl, None) == _lib.FDAS_INVALID_ARG
+    assert na(sp, None, 4, cap, bk, 85, 256, 2048, pl, None) == _lib.FDAS_INVALID_ARG
+    assert na(sp, _fake(0x5000), 4, cap, bk, 85, 256, 1000, pl, None) == _lib.FDAS_UNSUPPORTED
+    assert na(sp, _fake(0x5000), 4, -1, bk, 85, 256, 2048, pl, None) == _lib.FDAS_INVALID_ARG
+    assert _lib.NOALLOC_MAX_SPECTRA == 65536
     # batched adjoint: workspace by the gradients wanted, validation first
     wb = L.fdas_backward_batched_workspace_bytes
     both, only_s, only_t = wb(cap, 4, 9, 128, 2048, 0, 3), wb(cap, 4, 9, 128, 2048, 0, 1), wb(cap, 4, 9, 128, 2048, 0, 2)
