@@ -34,19 +34,21 @@ ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
 
-# LDS: 64 banks x 4 B per clock per CU (the bank structure the kernels' LDS
-# layout is built for), 256 CUs, 2.4 GHz
-LDS_PEAK_GBS = 256 * 64 * 4 * 2.4e9 / 1e9
+# LDS, as measured on gfx950 with single-wave probes and SQ_LDS_BANK_CONFLICT:
+# 64-bit reads are served 32 lanes per clock (64 banks x 4 B = 256 B per clock
+# per CU), 64-bit writes 16 lanes per clock (128 B per clock); 256 CUs, 2.4 GHz
+LDS_READ_PEAK_GBS = 256 * 256 * 2.4e9 / 1e9
+LDS_WRITE_PEAK_GBS = 256 * 128 * 2.4e9 / 1e9
 
 
 def forward_lds_bytes(N: int, K: int, M: int, L: int) -> int:
-    """LDS bytes one forward launch moves: every transform of a segment (the
-    window's and one inverse per template) exchanges its L complex values
-    through LDS twice (write + read, 8 B each) at L = 2048 and 4096 (three
-    radix passes); at other L the pass count differs and this is a lower
-    bound."""
+    """LDS bytes one forward launch writes (and reads again): every transform
+    of a segment (the window's and one inverse per template) exchanges its L
+    complex values through LDS twice (8 B each way) at L = 2048 and 4096
+    (three radix passes); at other L the pass count differs and this is a
+    lower bound."""
     S = -(-N // (L - M))
-    return S * (K + 1) * 2 * 2 * L * 8
+    return S * (K + 1) * 2 * L * 8
 
 
 # Real-time series counts of the paper's custom-FFT FDAS on a P100 for
@@ -92,13 +94,15 @@ def backward_work(N: int, K: int, M: int, L: int, want_taps: bool):
     L - M owned bins: the window's FFT and, per template, the multiply, the
     inverse FFT that recomputes y, g = 2 w y (2 flop/elem), FFT(g) and the
     accumulate (8 flop/elem); one inverse FFT of the accumulator per window.
-    The taps gradient adds, per template and window, a conjugate multiply
-    and an inverse FFT."""
+    The taps gradient adds, per template and window, the accumulation of
+    X conj(G) in the frequency domain (8 flop/elem), and one inverse FFT per
+    template (the transform is linear, so the windows' lags need only one;
+    the library runs one per template and group of windows)."""
     S = -(-N // (L - M))
     bytes_ = 8 * N + 4 * K * N + 8 * K * L + 8 * N + (8 * K * M if want_taps else 0)
     flops = S * 2 * fft_flops(L) + S * K * (2 * fft_flops(L) + 16 * L)
     if want_taps:
-        flops += S * K * (fft_flops(L) + 6 * L)
+        flops += S * K * 8 * L + K * fft_flops(L)
     return bytes_, flops
 
 
@@ -912,9 +916,12 @@ def main() -> int:
     alu["frac"] = None if valu is None else round(alu["achieved"] / VALU_PEAK_LANE_OPS, 4)
     alu["flop_model_TFLOPs"] = round(flops / ksec / 1e12, 3)
     lds_b = forward_lds_bytes(N, K, M, L)
-    lds = {"bound": "lds", "achieved": round(lds_b / ksec / 1e9, 1), "peak": round(LDS_PEAK_GBS, 1),
-           "unit": "GB/s", "bytes_per_launch": lds_b}
-    lds["frac"] = round(lds["achieved"] / lds["peak"], 4)
+    # LDS busy fraction: the writes at the write rate plus the reads at the
+    # read rate, over the launch time
+    lds = {"bound": "lds", "unit": "fraction of LDS time", "write_bytes_per_launch": lds_b,
+           "read_bytes_per_launch": lds_b, "write_peak_GBps": round(LDS_WRITE_PEAK_GBS, 1),
+           "read_peak_GBps": round(LDS_READ_PEAK_GBS, 1)}
+    lds["frac"] = round((lds_b / LDS_WRITE_PEAK_GBS + lds_b / LDS_READ_PEAK_GBS) / 1e9 / ksec, 4)
 
     stream_peaks = hbm_stream(fdas, torch, 4 << 30, max(5, args.steps // 2))
     print(f"# streaming probes: {json.dumps(stream_peaks)}", file=sys.stderr, flush=True)

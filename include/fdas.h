@@ -588,6 +588,22 @@ int fdas_find_candidates_batched(const float *sums_dev, const int64_t *offsets_d
 int fdas_stream_write(float *dst_dev, int64_t n, float value, hipStream_t stream);
 int fdas_stream_read(const float *src_dev, int64_t n, float *sums_dev, hipStream_t stream);
 
+/*
+ * LDS bank probe (measurement helper, not part of the correlation): the
+ * bank rules that the segment transforms' LDS layout is built for were
+ * measured with it.  `groups` single-wave workgroups each fill a 64 KB LDS
+ * array, then lane l repeats `iters` times one access at element
+ * pattern_dev[l] (64 int32 on the device; an element is 8 bytes for
+ * mode 0 = 64-bit write and mode 1 = 64-bit read, 16 bytes for
+ * mode 2 = 128-bit write; indices are masked into the array, so any pattern
+ * stays in bounds), with a wave barrier between repetitions.
+ * cycles_dev[g] (int64, `groups` entries) receives workgroup g's loop time
+ * in clock64 cycles; sink_dev (64 * groups floats) keeps the reads live.
+ * 1 <= iters <= 2^20, 1 <= groups <= 2^16, else FDAS_INVALID_ARG.
+ */
+int fdas_lds_probe(const int *pattern_dev, int mode, int iters, int groups,
+                   long long *cycles_dev, float *sink_dev, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,7 @@ from ._lib import (FdasError, fdas_backward_workspace_bytes, fdas_bank_elems,  #
                    fdas_r2c_batched_workspace_bytes, fdas_correlate_backward_batched,
                    fdas_backward_batched_workspace_bytes, fdas_autotune_batched,
                    fdas_autotune_candidates, fdas_batched_resident_grid,
-                   fdas_correlate_batched_noalloc, lib)
+                   fdas_correlate_batched_noalloc, fdas_lds_probe, lib)
 
 
 def make_bank(zmax: float, dz: float, M: int, L: int, device="cuda"):

@@ -75,6 +75,7 @@ SIGNATURES = [
     ("fdas_r2c_batched", _I, [_P, _I64, _I, ctypes.c_float, _P, _P, _SZ, _P]),
     ("fdas_stream_write", _I, [_P, _I64, ctypes.c_float, _P]),
     ("fdas_stream_read", _I, [_P, _I64, _P, _P]),
+    ("fdas_lds_probe", _I, [_P, _I, _I, _I, _P, _P, _P]),
 ]
 
 # partial sums written by fdas_stream_read
@@ -562,3 +563,17 @@ def fdas_stream_read(src, sums, stream=None) -> None:
     _require(sums, torch.float32, "sums", STREAM_PARTIALS)
     _check(lib().fdas_stream_read(_ptr(src), src.numel(), _ptr(sums), _stream(stream, src)),
            "fdas_stream_read")
+
+
+def fdas_lds_probe(pattern, mode: int, iters: int, groups: int, cycles, sink,
+                   stream=None) -> None:
+    """LDS bank probe: pattern int32[64] (device), mode 0/1/2 = 64-bit
+    write / 64-bit read / 128-bit write; cycles int64[groups], sink
+    float32[64 * groups]."""
+    import torch
+    _require(pattern, torch.int32, "pattern", 64)
+    _require(cycles, torch.int64, "cycles", groups)
+    _require(sink, torch.float32, "sink", 64 * groups)
+    _check(lib().fdas_lds_probe(_ptr(pattern), mode, iters, groups, _ptr(cycles), _ptr(sink),
+                                _stream(stream, pattern)),
+           "fdas_lds_probe")

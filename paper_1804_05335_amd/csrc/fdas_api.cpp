@@ -1005,3 +1005,21 @@ int fdas_stream_read(const float* src_dev, int64_t n, float* sums_dev, hipStream
 }
 
 }  // extern "C"
+
+int fdas_lds_probe(const int* pattern_dev, int mode, int iters, int groups,
+                   long long* cycles_dev, float* sink_dev, hipStream_t stream)
+{
+    if (mode < 0 || mode > 2)
+        return fail(FDAS_INVALID_ARG, "mode = %d is not 0, 1 or 2", mode);
+    if (iters < 1 || iters > (1 << 20) || groups < 1 || groups > (1 << 16))
+        return fail(FDAS_INVALID_ARG, "iters = %d or groups = %d out of range", iters, groups);
+    if (!pattern_dev || !cycles_dev || !sink_dev)
+        return fail(FDAS_INVALID_ARG, "pattern, cycles and sink must not be NULL");
+    if (!aligned(pattern_dev, 4) || !aligned(cycles_dev, 8) || !aligned(sink_dev, 4))
+        return fail(FDAS_INVALID_ARG, "misaligned pointer");
+    const hipError_t e = fdas::launch_lds_probe(pattern_dev, mode, iters, groups, cycles_dev,
+                                                sink_dev, stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "LDS probe launch");
+    return ok();
+}

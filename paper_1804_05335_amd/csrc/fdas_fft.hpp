@@ -242,44 +242,73 @@ __device__ __forceinline__ void dft_mul(float2 (&x)[R], const float2 (&w)[R])
 template <int... Rs>
 struct Radices {};
 
-// Number of register twiddles a lane keeps for the passes from NS on.
-template <int L, int E, int NS, class RL>
+// Number of register twiddles a lane keeps for the passes from NS on (the
+// pass whose stride is LNS takes its twiddles from an LDS table instead).
+template <int L, int E, int NS, int LNS, class RL>
 struct TwiddleCount;
-template <int L, int E, int NS>
-struct TwiddleCount<L, E, NS, Radices<>> {
+template <int L, int E, int NS, int LNS>
+struct TwiddleCount<L, E, NS, LNS, Radices<>> {
     static constexpr int value = 0;
 };
-template <int L, int E, int NS, int R, int... Rest>
-struct TwiddleCount<L, E, NS, Radices<R, Rest...>> {
-    static constexpr int value = (NS > 1 ? (E / R) * (R - 1) : 0) +
-                                 TwiddleCount<L, E, NS * R, Radices<Rest...>>::value;
+template <int L, int E, int NS, int LNS, int R, int... Rest>
+struct TwiddleCount<L, E, NS, LNS, Radices<R, Rest...>> {
+    static constexpr int value = (NS > 1 && NS != LNS ? (E / R) * (R - 1) : 0) +
+                                 TwiddleCount<L, E, NS * R, LNS, Radices<Rest...>>::value;
 };
 
-// LDS index: the low five bits (32 complex values = 64 banks) XORed with a
-// function g of the 32-value block number h.  A bijection on [0, L), so no
-// padding.  A contiguous 32-value row stays a permutation of the banks; for
-// the exchanges' writes -- stride R in the first pass, blocks NS apart
-// later -- g's low three bits follow h and bits 3, 4 fold h's bit 3 into
-// bits 1, 2, which keeps each half-wave on distinct banks for the E = 8 and
-// E = 16 plans.
+// LDS index of transform value idx.  gfx950 serves a 64-bit LDS read in
+// two passes of 32 lanes over 64 four-byte banks, a 64-bit write in four
+// passes of 16 lanes over 32 banks and a 128-bit write in eight passes of 8
+// lanes (measured), so an exchange is conflict-free when each 32-lane group
+// of a read touches 32 distinct values mod 32, each 16-lane group of a 64-bit
+// write 16 distinct values mod 16, and each 8-lane group of a 128-bit write 8
+// distinct value pairs mod 8.  Both maps XOR the low bits of idx with a
+// GF(2)-linear function of h = idx >> 4, which permutes every aligned
+// 16-value block (so the row reads, aligned 32-value blocks, stay
+// conflict-free); the function's columns are chosen so that the strided
+// writes of every plan -- stride 4, 8 or 16 in the first pass, runs of 4 or
+// 8 values 16 or 64 apart in the second -- fall on distinct banks:
+//   PAIR = false (64-bit writes throughout): bits 0..3 XOR G(h & 15), columns
+//     G(1) = 5, G(2) = 10, G(4) = 12, G(8) = 1;
+//   PAIR = true (the first pass writes adjacent pairs (2q, 2q + 1) as one
+//     128-bit store, so bit 0 must stay): bits 1..3 XOR 2 G(h & 7), columns
+//     G(1) = 3, G(2) = 6, G(4) = 4.
+template <bool PAIR>
 __device__ __forceinline__ int lds_pad(int idx)
 {
-    const int h = idx >> 5;
-    const int g = (h & 7) | ((((h >> 1) ^ (h >> 3)) & 1) << 3) | ((((h >> 2) ^ (h >> 3)) & 1) << 4);
-    return idx ^ g;
+    const int h = idx >> 4;
+    if constexpr (PAIR) {
+        const int g = ((h & 1) ? 3 : 0) ^ ((h & 2) ? 6 : 0) ^ ((h & 4) ? 4 : 0);
+        return idx ^ (g << 1);
+    } else {
+        const int g = ((h & 1) ? 5 : 0) ^ ((h & 2) ? 10 : 0) ^ ((h & 4) ? 12 : 0) ^
+                      ((h & 8) ? 1 : 0);
+        return idx ^ g;
+    }
 }
+
+// The first pass stores adjacent output pairs with 128-bit writes at
+// L = 8192 only.  Measured: there it frees the registers that the 64-bit
+// stores' extra addresses take (the 8-wave workgroups run short of them);
+// at L <= 4096 the 64-bit stores timed faster.
+template <int L>
+struct PairWrites {
+    static constexpr bool value = L >= 8192;
+};
 
 template <int L>
 struct LdsSize {
     static constexpr int value = L;
 };
 
-// Load the twiddles for passes NS.. into tw[OFF..].
-template <int L, int E, int NS, int OFF, int NTW, int R, int... Rest>
+// Load the twiddles for passes NS.. into tw[OFF..] (all but the pass of
+// stride LNS).
+template <int L, int E, int NS, int OFF, int NTW, int LNS, int R, int... Rest>
 __device__ __forceinline__ void load_twiddles(float2 (&tw)[NTW], const float2* __restrict__ table, int t)
 {
     constexpr int T = L / E, NB = E / R;
-    if constexpr (NS > 1) {
+    constexpr bool REG = NS > 1 && NS != LNS;
+    if constexpr (REG) {
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
             const int j = t + u * T;
@@ -290,7 +319,8 @@ __device__ __forceinline__ void load_twiddles(float2 (&tw)[NTW], const float2* _
         }
     }
     if constexpr (sizeof...(Rest) > 0)
-        load_twiddles<L, E, NS * R, OFF + (NS > 1 ? NB * (R - 1) : 0), NTW, Rest...>(tw, table, t);
+        load_twiddles<L, E, NS * R, OFF + (REG ? NB * (R - 1) : 0), NTW, LNS, Rest...>(tw, table,
+                                                                                     t);
 }
 
 // Run the passes from NS on.  The first of them reads `in` (positions
@@ -304,26 +334,39 @@ struct NoHook {
     __device__ void operator()() const {}
 };
 
-template <int L, int E, bool INV, int MODE0, int NS, int OFF, int NTW, class Hook, int R,
+template <int L, int E, bool INV, int MODE0, int NS, int OFF, int NTW, int LNS, class Hook, int R,
           int... Rest>
 __device__ __forceinline__ void run_passes(const float2 (&in)[E], const float2 (&pre)[E],
                                            float2 (&v)[E], float2*& lds_a, float2*& lds_b,
-                                           const float2 (&tw)[NTW], int t, Hook& hook)
+                                           const float2 (&tw)[NTW],
+                                           const float2* __restrict__ twl, int t, Hook& hook)
 {
     constexpr int T = L / E, NB = E / R;
     constexpr bool LAST = sizeof...(Rest) == 0;
+    constexpr bool REG = NS > 1 && NS != LNS;
+    constexpr bool PAIR = PairWrites<L>::value;
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
         float2 x[R];
 #pragma unroll
         for (int i = 0; i < R; ++i)
             x[i] = in[u + i * NB];
-        if constexpr (NS > 1) {
+        if constexpr (REG) {
             float2 w[R];
             w[0] = make_float2(1.f, 0.f);
 #pragma unroll
             for (int i = 1; i < R; ++i)
                 w[i] = tw[OFF + u * (R - 1) + (i - 1)];
+            dft_mul<R, INV, INV ? kMulConj : kMul, true>(x, w);
+        } else if constexpr (NS > 1) {
+            // twiddles W_L^((j mod NS) i L / (NS R)) from the LDS table
+            // (entries W_L^n, n < NS)
+            const int base = ((t + u * T) & (NS - 1)) * (L / (NS * R));
+            float2 w[R];
+            w[0] = make_float2(1.f, 0.f);
+#pragma unroll
+            for (int i = 1; i < R; ++i)
+                w[i] = twl[base * i];
             dft_mul<R, INV, INV ? kMulConj : kMul, true>(x, w);
         } else if constexpr (MODE0 != kNoMul) {
             float2 w[R];
@@ -339,12 +382,21 @@ __device__ __forceinline__ void run_passes(const float2 (&in)[E], const float2 (
 #pragma unroll
             for (int i = 0; i < R; ++i)
                 v[u + i * NB] = x[i];
+        } else if constexpr (NS == 1 && PAIR) {
+            // butterfly j's outputs are the contiguous values j R .. j R + R - 1:
+            // adjacent pairs go out as single 128-bit stores
+            const int j = t + u * T;
+            float4* dst = reinterpret_cast<float4*>(lds_a);
+#pragma unroll
+            for (int q = 0; q < R / 2; ++q)
+                dst[lds_pad<PAIR>(j * R + 2 * q) >> 1] =
+                    make_float4(x[2 * q].x, x[2 * q].y, x[2 * q + 1].x, x[2 * q + 1].y);
         } else {
             const int j = t + u * T;
             const int idxD = (j / NS) * (NS * R) + (j & (NS - 1));
 #pragma unroll
             for (int i = 0; i < R; ++i)
-                lds_a[lds_pad(idxD + i * NS)] = x[i];
+                lds_a[lds_pad<PAIR>(idxD + i * NS)] = x[i];
         }
     }
     if constexpr (NS == 1)
@@ -353,63 +405,96 @@ __device__ __forceinline__ void run_passes(const float2 (&in)[E], const float2 (
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < E; ++m)
-            v[m] = lds_a[lds_pad(t + m * T)];
+            v[m] = lds_a[lds_pad<PAIR>(t + m * T)];
         float2* tmp = lds_a;
         lds_a = lds_b;
         lds_b = tmp;
         NoHook none;
-        run_passes<L, E, INV, kNoMul, NS * R, OFF + (NS > 1 ? NB * (R - 1) : 0), NTW, NoHook,
-                   Rest...>(v, pre, v, lds_a, lds_b, tw, t, none);
+        run_passes<L, E, INV, kNoMul, NS * R, OFF + (REG ? NB * (R - 1) : 0), NTW, LNS, NoHook,
+                   Rest...>(v, pre, v, lds_a, lds_b, tw, twl, t, none);
     }
 }
 
 template <int L, int E, class RL>
 struct FFT;
 
+template <int... Rs>
+struct LastRadix;
+template <int R>
+struct LastRadix<R> {
+    static constexpr int value = R;
+};
+template <int R, int R2, int... Rest>
+struct LastRadix<R, R2, Rest...> {
+    static constexpr int value = LastRadix<R2, Rest...>::value;
+};
+
 template <int L, int E, int... Rs>
 struct FFT<L, E, Radices<Rs...>> {
     static constexpr int T = L / E;
-    static constexpr int NTW = TwiddleCount<L, E, 1, Radices<Rs...>>::value > 0
-                                   ? TwiddleCount<L, E, 1, Radices<Rs...>>::value : 1;
+    // At L = 8192 the last pass is radix 2 with stride NS = L/2; its
+    // twiddles W_L^n (n < L/2, one per butterfly) come from a 32 KB table in
+    // LDS, which frees the registers the longest transform runs short of.
+    static constexpr int kLNS = (L >= 8192 && LastRadix<Rs...>::value == 2) ? L / 2 : 0;
+    static constexpr int kLdsTw = kLNS;                 // table entries
+    static constexpr int kLdsTwAlloc = kLdsTw > 0 ? kLdsTw : 1;
+    static constexpr int NTW = TwiddleCount<L, E, 1, kLNS, Radices<Rs...>>::value > 0
+                                   ? TwiddleCount<L, E, 1, kLNS, Radices<Rs...>>::value : 1;
     static_assert((1 * ... * Rs) == L, "radices must multiply to L");
     static_assert(((E % Rs == 0) && ...), "every radix must divide E");
 
-    __device__ static void twiddles(float2 (&tw)[NTW], const float2* __restrict__ table, int t)
+    // A lane's twiddles: registers, plus the workgroup's LDS table.
+    struct TW {
+        float2 r[NTW];
+        const float2* lds;
+    };
+
+    // Load the register twiddles and, if the plan has one, fill the LDS
+    // table lds_table[kLdsTw] from the twiddle row (every lane takes part;
+    // the caller synchronises the workgroup before the first transform).
+    __device__ static void twiddles(TW& tw, const float2* __restrict__ table, float2* lds_table,
+                                    int t)
     {
-        load_twiddles<L, E, 1, 0, NTW, Rs...>(tw, table, t);
+        load_twiddles<L, E, 1, 0, NTW, kLNS, Rs...>(tw.r, table, t);
+        if constexpr (kLdsTw > 0) {
+            for (int n = t; n < kLdsTw; n += T)
+                lds_table[n] = table[n];
+        }
+        tw.lds = lds_table;
     }
     // transform of v (forward: INV = false)
     template <bool INV>
-    __device__ static void run(float2 (&v)[E], float2*& lds_a, float2*& lds_b,
-                               const float2 (&tw)[NTW], int t)
+    __device__ static void run(float2 (&v)[E], float2*& lds_a, float2*& lds_b, const TW& tw, int t)
     {
         NoHook none;
-        run_passes<L, E, INV, kNoMul, 1, 0, NTW, NoHook, Rs...>(v, v, v, lds_a, lds_b, tw, t, none);
+        run_passes<L, E, INV, kNoMul, 1, 0, NTW, kLNS, NoHook, Rs...>(v, v, v, lds_a, lds_b, tw.r,
+                                                                      tw.lds, t, none);
     }
     // as run; hook() runs once the first pass has read v
     template <bool INV, class Hook>
-    __device__ static void run_hook(float2 (&v)[E], float2*& lds_a, float2*& lds_b,
-                                    const float2 (&tw)[NTW], int t, Hook& hook)
+    __device__ static void run_hook(float2 (&v)[E], float2*& lds_a, float2*& lds_b, const TW& tw,
+                                    int t, Hook& hook)
     {
-        run_passes<L, E, INV, kNoMul, 1, 0, NTW, Hook, Rs...>(v, v, v, lds_a, lds_b, tw, t, hook);
+        run_passes<L, E, INV, kNoMul, 1, 0, NTW, kLNS, Hook, Rs...>(v, v, v, lds_a, lds_b, tw.r,
+                                                                    tw.lds, t, hook);
     }
     // v = transform of in[m] * pre[m] (MODE kMul) or in[m] * conj(pre[m]) (kMulConj)
     template <bool INV, int MODE>
     __device__ static void run_mul(const float2 (&in)[E], const float2 (&pre)[E], float2 (&v)[E],
-                                   float2*& lds_a, float2*& lds_b, const float2 (&tw)[NTW], int t)
+                                   float2*& lds_a, float2*& lds_b, const TW& tw, int t)
     {
         NoHook none;
-        run_passes<L, E, INV, MODE, 1, 0, NTW, NoHook, Rs...>(in, pre, v, lds_a, lds_b, tw, t,
-                                                              none);
+        run_passes<L, E, INV, MODE, 1, 0, NTW, kLNS, NoHook, Rs...>(in, pre, v, lds_a, lds_b,
+                                                                    tw.r, tw.lds, t, none);
     }
     // as run_mul; hook() runs once the first pass has consumed `in` and `pre`
     template <bool INV, int MODE, class Hook>
     __device__ static void run_mul_hook(const float2 (&in)[E], const float2 (&pre)[E],
                                         float2 (&v)[E], float2*& lds_a, float2*& lds_b,
-                                        const float2 (&tw)[NTW], int t, Hook& hook)
+                                        const TW& tw, int t, Hook& hook)
     {
-        run_passes<L, E, INV, MODE, 1, 0, NTW, Hook, Rs...>(in, pre, v, lds_a, lds_b, tw, t,
-                                                            hook);
+        run_passes<L, E, INV, MODE, 1, 0, NTW, kLNS, Hook, Rs...>(in, pre, v, lds_a, lds_b, tw.r,
+                                                                  tw.lds, t, hook);
     }
 };
 
@@ -446,6 +531,9 @@ struct Geometry {
 #ifndef FDAS_BWD_WAVES
 #define FDAS_BWD_WAVES 2
 #endif
+#ifndef FDAS_BWD_GROUP
+#define FDAS_BWD_GROUP 3
+#endif
 #ifndef FDAS_BWD_E8192
 #define FDAS_BWD_E8192 16
 #endif
@@ -455,6 +543,12 @@ struct BwdGeometry {
     static constexpr int kMinWaves = L >= 8192 ? 1 : FDAS_BWD_WAVES;
     // spectrum gradient only: no taps transform, fits 168 VGPRs up to L = 2048
     static constexpr int kMinWavesSpec = L >= 8192 ? 1 : (L >= 4096 ? FDAS_BWD_WAVES : 3);
+    // windows per workgroup of the two-gradient adjoint (they share one taps
+    // transform per template), for the edge-specialised kernel (M/2 = T)
+    // where a workgroup is a single wave: measured at L = 512, M = 128 (2^20
+    // bins, K = 85) 1 / 2 / 3 / 4 windows took 0.349 / 0.387 / 0.300 /
+    // 0.669 ms (two waves per SIMD from two windows on, spills at four)
+    static constexpr int kWinGroupEdge = L <= 512 ? FDAS_BWD_GROUP : 1;
 };
 
 }  // namespace fdas

@@ -50,7 +50,8 @@ hipError_t launch_batched(const float2* specs, const int64_t* offsets, int nspec
 // file-scope device array; looked up on the first call on each device).
 hipError_t noalloc_segpre(int64_t** out);
 
-// Adjoint: window kernel into partA [nzc][nwin][L] / partT [nwin][K][M], then
+// Adjoint: window kernel into partA [nzc][nwin][L] / partT [ceil(nwin / G)][K][M]
+// (G = backward_window_group(L, M)), then
 // the FP64 reductions into grad_spec [N] / grad_taps [K][M] (either may be
 // null); the taps reduction sums tsplit window chunks into tpart
 // [tsplit][K][M] (FP64) first.
@@ -58,6 +59,11 @@ hipError_t launch_backward(const float2* spec, int64_t N, const float2* bank, in
                           int L, const float* dLdP, float2* grad_spec, float2* grad_taps,
                           int zchunk, float2* partA, float2* partT, int tsplit, double2* tpart,
                           hipStream_t s);
+
+// Windows per workgroup of the two-gradient adjoint at segment length L and
+// M taps (they share one taps transform per template; partT has one [K][M]
+// row per group of this many windows).
+int backward_window_group(int L, int M);
 
 // Batched adjoint over the spectra of a batched forward: window scan into
 // winpre [nspec + 1], the persistent window kernel into partA
@@ -103,5 +109,8 @@ hipError_t launch_candidates_batched(const float* sums, const int64_t* offsets, 
 // sums[FDAS_STREAM_PARTIALS] (one partial per workgroup).
 hipError_t launch_stream_write(float* dst, int64_t n, float value, hipStream_t s);
 hipError_t launch_stream_read(const float* src, int64_t n, float* sums, hipStream_t s);
+// LDS bank probe (mode 0/1/2: 64-bit write / 64-bit read / 128-bit write).
+hipError_t launch_lds_probe(const int* pattern, int mode, int iters, int groups,
+                            long long* cycles, float* sink, hipStream_t s);
 
 }  // namespace fdas

@@ -191,7 +191,7 @@ struct Fwd {
     template <bool IB, bool SYM = false, bool DUAL = false, int DEAD = 0>
     __device__ static void item(const float2* __restrict__ spec, int64_t N,
                                 const float2* __restrict__ bank, int K, int M, int64_t s, int z0,
-                                int z1, float* __restrict__ plane, const float2 (&tw)[NTW],
+                                int z1, float* __restrict__ plane, const typename F::TW& tw,
                                 float2*& la, float2*& lb, int t, float2 (&H)[E],
                                 const float2* __restrict__ bank2 = nullptr)
     {
@@ -338,15 +338,17 @@ __global__ __launch_bounds__(Fwd<L>::T, 2) void forward_kernel(
     int64_t nseg, float* __restrict__ plane, const float2* __restrict__ bank2)
 {
     using W = Fwd<L>;
-    __shared__ float2 lds[2][LdsSize<L>::value];
+    __shared__ __align__(16) float2 lds[2][LdsSize<L>::value];
+    __shared__ float2 twl[W::F::kLdsTwAlloc];
     int64_t i, i1;
     item_range(nseg * K, i, i1);
     if (i >= i1)
         return;     // uniform across the workgroup, before any barrier
     const int t = threadIdx.x;
-    float2 tw[W::NTW];
+    typename W::F::TW tw;
     const int rows = SYM ? (K + 1) / 2 : K;      // bank rows before the twiddle row
-    W::F::twiddles(tw, bank + (int64_t)rows * L, t);
+    W::F::twiddles(tw, bank + (int64_t)rows * L, twl, t);
+    __syncthreads();
     float2* la = lds[0];
     float2* lb = lds[1];
     float2 H[W::E];
@@ -446,14 +448,16 @@ __global__ __launch_bounds__((Fwd<L, E>::T), 2) void batched_kernel(
     int K, int M, float* __restrict__ planes)
 {
     using W = Fwd<L, E>;
-    __shared__ float2 lds[2][LdsSize<L>::value];
+    __shared__ __align__(16) float2 lds[2][LdsSize<L>::value];
+    __shared__ float2 twl[W::F::kLdsTwAlloc];
     int64_t i, i1;
     item_range(segpre[nspec] * K, i, i1);
     if (i >= i1)
         return;
     const int t = threadIdx.x;
-    float2 tw[W::NTW];
-    W::F::twiddles(tw, bank + (int64_t)K * L, t);
+    typename W::F::TW tw;
+    W::F::twiddles(tw, bank + (int64_t)K * L, twl, t);
+    __syncthreads();
     float2* la = lds[0];
     float2* lb = lds[1];
     float2 H[W::E];
@@ -511,7 +515,7 @@ struct Bwd {
                                 const float2* __restrict__ bank, int M, int64_t s, int z0,
                                 int z1, const float* __restrict__ dLdP, bool want_A,
                                 float2* __restrict__ partA,
-                                float2* __restrict__ partT, const float2 (&tw)[NTW],
+                                float2* __restrict__ partT, const typename F::TW& tw,
                                 float2*& la, float2*& lb, int t, float2 (&Hc)[E])
     {
         const int B = L - M;
@@ -583,6 +587,127 @@ struct Bwd {
                 partA[t + T * m] = acc[m];
         }
     }
+
+    // One window of a group: its spectrum, bin count, window index in that
+    // spectrum, weights and partial-gradient row.  n = 0 marks an absent
+    // window (the group's tail past the last window).
+    struct Win {
+        const float2* spec;
+        int64_t N;
+        int64_t s;
+        const float* dLdP;
+        float2* partA;
+    };
+
+    // Both gradients for NW windows at once.  The taps gradient of template
+    // z is sum_s IFFT(X_s conj(G_{z,s})) at the lags; the inverse transform
+    // is linear, so the group accumulates P_z = sum_s X_s conj(G_{z,s}) in
+    // the frequency domain and runs one inverse transform per template for
+    // all its windows: 2 + 1/NW transforms per (window, template) instead
+    // of 3, and partT holds one [K][M] row per group instead of per window.
+    // The spectrum gradient is computed exactly as by item(), window by
+    // window (bitwise the same partials).
+    template <bool EDGE, int NW>
+    __device__ static void item_group(const Win (&win)[NW], const float2* __restrict__ bank,
+                                      int M, int z0, int z1, bool want_A,
+                                      float2* __restrict__ partT, const typename F::TW& tw,
+                                      float2*& la, float2*& lb, int t, float2 (&Hc)[E])
+    {
+        const int B = L - M;
+        float2 X[NW][E];
+        float2 acc[NW][E];
+        int nvalid[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const int64_t out0 = win[w].s * B;
+            nvalid[w] = win[w].spec ? (int)min<int64_t>(B, win[w].N - out0) : 0;
+            if (win[w].spec) {
+                W::load_window(X[w], win[w].spec, win[w].N, out0 - M / 2, t);
+                F::template run<false>(X[w], la, lb, tw, t);
+            }
+#pragma unroll
+            for (int m = 0; m < E; ++m)
+                acc[w][m] = make_float2(0.f, 0.f);
+        }
+
+        for (int z = z0; z < z1; ++z) {
+            float2 P[E];
+#pragma unroll
+            for (int m = 0; m < E; ++m)
+                P[m] = make_float2(0.f, 0.f);
+            float2 Hn[E];
+            const int zn = z + 1 < z1 ? z + 1 : z0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                if (!win[w].spec)           // uniform: the group's tail
+                    continue;
+                const int64_t out0 = win[w].s * B;
+                const auto rw = seg_rsrc(win[w].dLdP + ((int64_t)z * win[w].N + out0 - M / 2),
+                                         (M / 2 + nvalid[w]) * 4);
+                float wv[E];
+#pragma unroll
+                for (int m = 0; m < E; ++m)
+                    wv[m] = (EDGE && (m == 0 || m == E - 1))
+                                ? 0.f
+                                : 2.f * __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                                            rw, seg_off<4>(t + T * m, M / 2), 0, kNonTemporal));
+                float2 v[E];
+                F::template run_mul<true, kMul>(X[w], Hc, v, la, lb, tw, t);   // y
+#pragma unroll
+                for (int m = 0; m < E; ++m)                                   // g = 2 w y
+                    v[m] = (EDGE && (m == 0 || m == E - 1))
+                               ? make_float2(0.f, 0.f)
+                               : make_float2(wv[m] * v[m].x, wv[m] * v[m].y);
+                if (w == NW - 1 || !win[w + 1 < NW ? w + 1 : w].spec) {
+                    auto next = [&]() { W::load_row(Hn, bank, zn, t); };
+                    F::template run_hook<false>(v, la, lb, tw, t, next);      // G = FFT(g)
+                } else {
+                    F::template run<false>(v, la, lb, tw, t);
+                }
+                if (want_A) {
+#pragma unroll
+                    for (int m = 0; m < E; ++m) {                             // acc += conj(H) G
+                        acc[w][m].x = fmaf(v[m].x, Hc[m].x, fmaf(v[m].y, Hc[m].y, acc[w][m].x));
+                        acc[w][m].y = fmaf(v[m].y, Hc[m].x, fmaf(-v[m].x, Hc[m].y, acc[w][m].y));
+                    }
+                }
+#pragma unroll
+                for (int m = 0; m < E; ++m) {                                 // P += X conj(G)
+                    P[m].x = fmaf(X[w][m].x, v[m].x, fmaf(X[w][m].y, v[m].y, P[m].x));
+                    P[m].y = fmaf(X[w][m].y, v[m].x, fmaf(-X[w][m].x, v[m].y, P[m].y));
+                }
+            }
+            F::template run<true>(P, la, lb, tw, t);                          // lags
+            float2* pz = partT + (int64_t)z * M;
+            if constexpr (EDGE) {
+                pz[t + M / 2] = P[0];
+                pz[t] = P[E - 1];
+            } else {
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int p = t + T * m;
+                    if (p < M / 2)
+                        pz[p + M / 2] = P[m];
+                    else if (p >= L - M / 2)
+                        pz[p - L + M / 2] = P[m];
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < E; ++m)
+                Hc[m] = Hn[m];
+        }
+        if (want_A) {
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                if (!win[w].spec)
+                    continue;
+                F::template run<true>(acc[w], la, lb, tw, t);
+#pragma unroll
+                for (int m = 0; m < E; ++m)
+                    win[w].partA[t + T * m] = acc[w][m];
+            }
+        }
+    }
 };
 
 template <int L, bool WANT_T, bool EDGE>
@@ -593,10 +718,12 @@ __global__ __launch_bounds__(Bwd<L>::T, WANT_T ? BwdGeometry<L>::kMinWaves
     float2* __restrict__ partA, float2* __restrict__ partT)
 {
     using Bk = Bwd<L>;
-    __shared__ float2 lds[2][LdsSize<L>::value];
+    __shared__ __align__(16) float2 lds[2][LdsSize<L>::value];
+    __shared__ float2 twl[Bk::F::kLdsTwAlloc];
     const int t = threadIdx.x;
-    float2 tw[Bk::NTW];
-    Bk::F::twiddles(tw, bank + (int64_t)K * L, t);
+    typename Bk::F::TW tw;
+    Bk::F::twiddles(tw, bank + (int64_t)K * L, twl, t);
+    __syncthreads();
     float2* la = lds[0];
     float2* lb = lds[1];
     const int64_t s = blockIdx.x;
@@ -605,9 +732,24 @@ __global__ __launch_bounds__(Bwd<L>::T, WANT_T ? BwdGeometry<L>::kMinWaves
     const int z1 = min(K, z0 + zchunk);
     float2 H[Bk::E];
     Bk::W::load_row(H, bank, z0, t);
-    Bk::template item<WANT_T, EDGE>(spec, N, bank, M, s, z0, z1, dLdP, want_A != 0,
-                              partA + ((int64_t)c * nwin + s) * L, partT + s * (int64_t)K * M, tw,
-                              la, lb, t, H);
+    constexpr int NW = WANT_T && EDGE ? BwdGeometry<L>::kWinGroupEdge : 1;
+    if constexpr (NW == 1) {
+        Bk::template item<WANT_T, EDGE>(spec, N, bank, M, s, z0, z1, dLdP, want_A != 0,
+                                        partA + ((int64_t)c * nwin + s) * L,
+                                        partT + s * (int64_t)K * M, tw, la, lb, t, H);
+    } else {
+        // workgroup x takes windows x NW .. x NW + NW - 1 (those below nwin)
+        typename Bk::Win win[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const int64_t sw = s * NW + w;
+            const bool ok = sw < nwin;
+            win[w] = {ok ? spec : nullptr, N, sw, dLdP,
+                      partA + ((int64_t)c * nwin + (ok ? sw : 0)) * L};
+        }
+        Bk::template item_group<EDGE, NW>(win, bank, M, z0, z1, want_A != 0,
+                                          partT + s * (int64_t)K * M, tw, la, lb, t, H);
+    }
 }
 
 // grad_A[k] = sum over chunks c and windows s covering k of
@@ -635,7 +777,8 @@ __global__ void reduce_grad_spec_kernel(const float2* __restrict__ partA, int64_
     grad[k] = make_float2((float)sr, (float)si);
 }
 
-// grad_T[z][j] = (1/L) sum_s partT[s][z][j] in FP64, in two fixed-order
+// grad_T[z][j] = (1/L) sum_s partT[s][z][j] in FP64 (s: the rows of partT,
+// one per window or per group of windows), in two fixed-order
 // stages.  Stage 1: block (x, y) covers kTapsCols consecutive (z, j) entries
 // and the windows s of chunk y; lane row q sums s = s0 + q, s0 + q +
 // kTapsRows, ..., the rows are added in order q = 0, 1, ..., and the FP64
@@ -646,13 +789,14 @@ constexpr int kTapsCols = 64, kTapsRows = 16;
 
 __global__ __launch_bounds__(kTapsCols * kTapsRows) void reduce_grad_taps_kernel(
     const float2* __restrict__ partT, int64_t nwin, const int64_t* __restrict__ nwin_dev,
-    int64_t chunk, int KM, double2* __restrict__ tpart)
+    int group, int64_t chunk, int KM, double2* __restrict__ tpart)
 {
     __shared__ double part[kTapsRows][kTapsCols][2];
     const int c = threadIdx.x % kTapsCols, q = threadIdx.x / kTapsCols;
     const int i = blockIdx.x * kTapsCols + c;
-    // batched: the windows actually present (a device count, at most nwin)
-    const int64_t nw = nwin_dev ? min(nwin, *nwin_dev) : nwin;
+    // rows present: nwin, or (batched) the groups of the windows actually
+    // present (a device window count, rows of `group` windows, at most nwin)
+    const int64_t nw = nwin_dev ? min(nwin, (*nwin_dev + group - 1) / group) : nwin;
     const int64_t s0 = (int64_t)blockIdx.y * chunk;
     const int64_t s1 = min(nw, s0 + chunk);
     double sr = 0.0, si = 0.0;
@@ -716,28 +860,52 @@ backward_batched_kernel(const float2* __restrict__ specs, const int64_t* __restr
                         float2* __restrict__ partT)
 {
     using Bk = Bwd<L>;
-    __shared__ float2 lds[2][LdsSize<L>::value];
+    __shared__ __align__(16) float2 lds[2][LdsSize<L>::value];
+    __shared__ float2 twl[Bk::F::kLdsTwAlloc];
     const int64_t nw = min(winpre[nspec], maxwin);
     const int c = blockIdx.y;
     const int z0 = c * zchunk;
     const int z1 = min(K, z0 + zchunk);
-    const int64_t g = (int64_t)blockIdx.z * gridDim.x + blockIdx.x;
-    if (g >= nw)
+    constexpr int NW = WANT_T && EDGE ? BwdGeometry<L>::kWinGroupEdge : 1;
+    const int64_t g = (int64_t)blockIdx.z * gridDim.x + blockIdx.x;   // window, or group
+    if (g * NW >= nw)
         return;     // uniform across the workgroup, before any barrier
     const int t = threadIdx.x;
-    float2 tw[Bk::NTW];
-    Bk::F::twiddles(tw, bank + (int64_t)K * L, t);
+    typename Bk::F::TW tw;
+    Bk::F::twiddles(tw, bank + (int64_t)K * L, twl, t);
+    __syncthreads();
     float2* la = lds[0];
     float2* lb = lds[1];
-    const int b = owner(winpre, nspec, g);
-    int64_t off, Nb;
-    spec_range(offsets, b, cap, off, Nb);
     float2 H[Bk::E];
     Bk::W::load_row(H, bank, z0, t);
-    Bk::template item<WANT_T, EDGE>(specs + off, Nb, bank, M, g - winpre[b], z0, z1,
-                                    dLdP + (int64_t)K * off, want_A != 0,
-                                    partA + ((int64_t)c * maxwin + g) * L,
-                                    partT + g * (int64_t)K * M, tw, la, lb, t, H);
+    if constexpr (NW == 1) {
+        const int b = owner(winpre, nspec, g);
+        int64_t off, Nb;
+        spec_range(offsets, b, cap, off, Nb);
+        Bk::template item<WANT_T, EDGE>(specs + off, Nb, bank, M, g - winpre[b], z0, z1,
+                                        dLdP + (int64_t)K * off, want_A != 0,
+                                        partA + ((int64_t)c * maxwin + g) * L,
+                                        partT + g * (int64_t)K * M, tw, la, lb, t, H);
+    } else {
+        // group g: global windows g NW .. g NW + NW - 1 (those below the
+        // batch's count), each from its own spectrum
+        typename Bk::Win win[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const int64_t gw = g * NW + w;
+            if (gw < nw) {
+                const int b = owner(winpre, nspec, gw);
+                int64_t off, Nb;
+                spec_range(offsets, b, cap, off, Nb);
+                win[w] = {specs + off, Nb, gw - winpre[b], dLdP + (int64_t)K * off,
+                          partA + ((int64_t)c * maxwin + gw) * L};
+            } else {
+                win[w] = {nullptr, 0, 0, nullptr, partA};
+            }
+        }
+        Bk::template item_group<EDGE, NW>(win, bank, M, z0, z1, want_A != 0,
+                                          partT + g * (int64_t)K * M, tw, la, lb, t, H);
+    }
 }
 
 // grad[k] for every packed bin k < cap: the bins of spectrum b (the last b
@@ -1073,15 +1241,17 @@ static hipError_t launch_backward_L(const float2* spec, int64_t N, const float2*
 {
     const int nzc = (K + zchunk - 1) / zchunk;
     const dim3 grid((unsigned)nwin, (unsigned)nzc);
+    const int NW = backward_window_group(L, M);
+    const dim3 grid_t((unsigned)((nwin + NW - 1) / NW), (unsigned)nzc);
     // The edge specialisation pays off with the taps transform (fewer
     // instructions and cycles); without it the compiler waits for the w
     // loads early in the transform and the kernel ran slower, so the
     // spectrum-only kernel keeps the general form.
     if (want_T && M / 2 == Bwd<L>::T)
-        hipLaunchKernelGGL((backward_kernel<L, true, true>), grid, dim3(Bwd<L>::T), 0, s, spec, N,
-                           bank, K, M, zchunk, nwin, dLdP, want_A, partA, partT);
+        hipLaunchKernelGGL((backward_kernel<L, true, true>), grid_t, dim3(Bwd<L>::T), 0, s, spec,
+                           N, bank, K, M, zchunk, nwin, dLdP, want_A, partA, partT);
     else if (want_T)
-        hipLaunchKernelGGL((backward_kernel<L, true, false>), grid, dim3(Bwd<L>::T), 0, s, spec,
+        hipLaunchKernelGGL((backward_kernel<L, true, false>), grid_t, dim3(Bwd<L>::T), 0, s, spec,
                            N, bank, K, M, zchunk, nwin, dLdP, want_A, partA, partT);
     else
         hipLaunchKernelGGL((backward_kernel<L, false, false>), grid, dim3(Bwd<L>::T), 0, s, spec,
@@ -1120,11 +1290,13 @@ hipError_t launch_backward(const float2* spec, int64_t N, const float2* bank, in
     }
     if (want_T) {
         const int KM = K * M;
-        const int64_t chunk = nwin > 0 ? (nwin + tsplit - 1) / tsplit : 1;
+        const int NW = backward_window_group(L, M);
+        const int64_t ngrp = (nwin + NW - 1) / NW;       // rows of partT
+        const int64_t chunk = ngrp > 0 ? (ngrp + tsplit - 1) / tsplit : 1;
         hipLaunchKernelGGL(reduce_grad_taps_kernel,
                            dim3((KM + kTapsCols - 1) / kTapsCols, (unsigned)tsplit),
-                           dim3(kTapsCols * kTapsRows), 0, s, partT, nwin,
-                           (const int64_t*)nullptr, chunk, KM, tpart);
+                           dim3(kTapsCols * kTapsRows), 0, s, partT, ngrp,
+                           (const int64_t*)nullptr, 1, chunk, KM, tpart);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         hipLaunchKernelGGL(reduce_grad_taps_final_kernel, dim3((KM + bs - 1) / bs), dim3(bs), 0,
@@ -1138,6 +1310,24 @@ hipError_t launch_backward(const float2* spec, int64_t N, const float2* bank, in
 constexpr int64_t kMaxBwdGridX = int64_t(1) << 22;
 
 template <int L>
+static int window_group_L(int M)
+{
+    return M / 2 == Bwd<L>::T ? BwdGeometry<L>::kWinGroupEdge : 1;
+}
+
+int backward_window_group(int L, int M)
+{
+    switch (L) {
+    case 256:  return window_group_L<256>(M);
+    case 512:  return window_group_L<512>(M);
+    case 1024: return window_group_L<1024>(M);
+    case 2048: return window_group_L<2048>(M);
+    case 4096: return window_group_L<4096>(M);
+    default:   return window_group_L<8192>(M);
+    }
+}
+
+template <int L>
 static hipError_t launch_backward_batched_L(const float2* specs, const int64_t* offsets,
                                             const int64_t* winpre, int nspec, int64_t cap,
                                             const float2* bank, int K, int M, int zchunk,
@@ -1146,17 +1336,23 @@ static hipError_t launch_backward_batched_L(const float2* specs, const int64_t* 
                                             hipStream_t s)
 {
     const int nzc = (K + zchunk - 1) / zchunk;
-    // one workgroup per (window, chunk): windows x + gridDim.x * z
-    const int64_t gx = maxwin < kMaxBwdGridX ? maxwin : kMaxBwdGridX;
-    const dim3 grid((unsigned)gx, (unsigned)nzc, (unsigned)((maxwin + gx - 1) / (gx > 0 ? gx : 1)));
+    // one workgroup per (window, chunk), or per (group of windows, chunk)
+    // with the taps gradient: items x + gridDim.x * z
+    auto grid_for = [&](int64_t items) {
+        const int64_t gx = items < kMaxBwdGridX ? items : kMaxBwdGridX;
+        return dim3((unsigned)gx, (unsigned)nzc, (unsigned)((items + gx - 1) / (gx > 0 ? gx : 1)));
+    };
     if (maxwin < 1)
         return hipSuccess;
+    const dim3 grid = grid_for(maxwin);
+    const int NW = backward_window_group(L, M);
+    const dim3 grid_t = grid_for((maxwin + NW - 1) / NW);
     if (want_T && M / 2 == Bwd<L>::T)
-        hipLaunchKernelGGL((backward_batched_kernel<L, true, true>), grid, dim3(Bwd<L>::T), 0, s,
-                           specs, offsets, winpre, nspec, cap, bank, K, M, zchunk, maxwin, dLdP,
+        hipLaunchKernelGGL((backward_batched_kernel<L, true, true>), grid_t, dim3(Bwd<L>::T), 0,
+                           s, specs, offsets, winpre, nspec, cap, bank, K, M, zchunk, maxwin, dLdP,
                            want_A, partA, partT);
     else if (want_T)
-        hipLaunchKernelGGL((backward_batched_kernel<L, true, false>), grid, dim3(Bwd<L>::T), 0,
+        hipLaunchKernelGGL((backward_batched_kernel<L, true, false>), grid_t, dim3(Bwd<L>::T), 0,
                            s, specs, offsets, winpre, nspec, cap, bank, K, M, zchunk, maxwin, dLdP,
                            want_A, partA, partT);
     else
@@ -1200,11 +1396,13 @@ hipError_t launch_backward_batched(const float2* specs, const int64_t* offsets, 
     }
     if (want_T) {
         const int KM = K * M;
-        const int64_t chunk = maxwin > 0 ? (maxwin + tsplit - 1) / tsplit : 1;
+        const int NW = backward_window_group(L, M);
+        const int64_t ngrp = (maxwin + NW - 1) / NW;     // rows of partT
+        const int64_t chunk = ngrp > 0 ? (ngrp + tsplit - 1) / tsplit : 1;
         hipLaunchKernelGGL(reduce_grad_taps_kernel,
                            dim3((KM + kTapsCols - 1) / kTapsCols, (unsigned)tsplit),
-                           dim3(kTapsCols * kTapsRows), 0, s, partT, maxwin,
-                           (const int64_t*)(winpre + nspec), chunk, KM, tpart);
+                           dim3(kTapsCols * kTapsRows), 0, s, partT, ngrp,
+                           (const int64_t*)(winpre + nspec), NW, chunk, KM, tpart);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         hipLaunchKernelGGL(reduce_grad_taps_final_kernel, dim3((KM + bs - 1) / bs), dim3(bs), 0,

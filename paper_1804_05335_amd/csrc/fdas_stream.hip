@@ -1,5 +1,5 @@
-// Streaming probes of the device memory: a write-only and a read-only pass
-// over a float buffer.  They measure the bandwidth that plain streaming
+// Measurement probes.  Streaming probes of the device memory: a write-only
+// and a read-only pass over a float buffer.  They measure the bandwidth that plain streaming
 // kernels reach on this device, the figure the correlation's plane write
 // and the harmonic gathers are compared with beside the published peak.
 //
@@ -7,6 +7,11 @@
 // grid-stride loop of 16-byte non-temporal loads on a fixed grid that fills
 // every CU several times over, and keeps its loads live by summing them:
 // one partial sum per workgroup, reduced through LDS.
+//
+// An LDS bank probe: one wave repeats one LDS access of a chosen width at
+// per-lane element indices the caller picks, and reports the clock cycles
+// of the loop, so access patterns can be compared for bank conflicts (the
+// rules the transforms' LDS layout follows were established with it).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -74,7 +79,60 @@ int read_grid(int64_t n)
                                                                          : FDAS_STREAM_PARTIALS));
 }
 
+// LDS bank probe: MODE 0/1 = 64-bit write/read, 2 = 128-bit write.  Each
+// lane's index is masked into the 64 KB array, so any pattern stays in
+// bounds.  The loop's accesses are kept (a wave barrier between them, the
+// reads summed into the output).
+constexpr int kProbeBytes = 65536;
+
+template <int MODE>
+__global__ __launch_bounds__(64) void lds_probe_kernel(const int* __restrict__ pattern, int iters,
+                                                       long long* __restrict__ cycles,
+                                                       float* __restrict__ sink)
+{
+    __shared__ __align__(16) float4 buf[kProbeBytes / 16];
+    const int l = threadIdx.x;
+    for (int i = l; i < kProbeBytes / 16; i += 64)
+        buf[i] = make_float4((float)i, 0.f, 0.f, 1.f);
+    __syncthreads();
+    float2* b2 = reinterpret_cast<float2*>(buf);
+    const int idx = pattern[l];
+    const int i2 = idx & (kProbeBytes / 8 - 1), i4 = idx & (kProbeBytes / 16 - 1);
+    float acc = 0.f;
+    const long long t0 = clock64();
+    for (int k = 0; k < iters; ++k) {
+        if constexpr (MODE == 0) {
+            b2[i2] = make_float2((float)k, (float)l);
+        } else if constexpr (MODE == 1) {
+            const float2 v = b2[i2];
+            acc += v.x + v.y;
+        } else {
+            buf[i4] = make_float4((float)k, (float)l, 0.f, 1.f);
+        }
+        __syncthreads();
+    }
+    const long long t1 = clock64();
+    sink[blockIdx.x * 64 + l] = acc + reinterpret_cast<float*>(buf)[l];
+    if (l == 0)
+        cycles[blockIdx.x] = t1 - t0;
+}
+
 }  // namespace
+
+hipError_t launch_lds_probe(const int* pattern, int mode, int iters, int groups,
+                            long long* cycles, float* sink, hipStream_t s)
+{
+    if (mode == 0)
+        hipLaunchKernelGGL(lds_probe_kernel<0>, dim3(groups), dim3(64), 0, s, pattern, iters,
+                           cycles, sink);
+    else if (mode == 1)
+        hipLaunchKernelGGL(lds_probe_kernel<1>, dim3(groups), dim3(64), 0, s, pattern, iters,
+                           cycles, sink);
+    else
+        hipLaunchKernelGGL(lds_probe_kernel<2>, dim3(groups), dim3(64), 0, s, pattern, iters,
+                           cycles, sink);
+    return hipGetLastError();
+}
 
 hipError_t launch_stream_write(float* dst, int64_t n, float value, hipStream_t s)
 {

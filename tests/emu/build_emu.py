@@ -28,5 +28,16 @@ def build() -> str:
     return OUT
 
 
+def build_lds_layout() -> str:
+    """The transforms' LDS index map alone (tests/emu/lds_layout.cpp)."""
+    out = os.path.join(HERE, "_build", "liblds_layout.so")
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    tmp = out + f".tmp{os.getpid()}"
+    subprocess.run([CXX, "-O1", "-std=c++20", "-fPIC", "-shared", "-I", HERE, "-x", "c++",
+                    os.path.join(HERE, "lds_layout.cpp"), "-o", tmp], check=True)
+    os.replace(tmp, out)
+    return out
+
+
 if __name__ == "__main__":
     print(build())

@@ -26,6 +26,8 @@
 
 struct float2 { float x, y; };
 inline float2 make_float2(float a, float b) { return float2{a, b}; }
+struct float4 { float x, y, z, w; };
+inline float4 make_float4(float a, float b, float c, float d) { return float4{a, b, c, d}; }
 struct double2 { double x, y; };
 inline double2 make_double2(double a, double b) { return double2{a, b}; }
 
@@ -110,6 +112,7 @@ inline int emu_ds_bpermute(int addr, int data)
     __syncthreads();
     return v;
 }
+inline long long clock64() { return 0; }
 inline unsigned atomicAdd(unsigned* p, unsigned v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
 inline void sincospi(double x, double* s, double* c) { *s = std::sin(M_PI * x); *c = std::cos(M_PI * x); }
 

@@ -144,6 +144,13 @@ def test_validation_happens_before_any_device_call():
     assert na(sp, _fake(0x5000), 4, cap, bk, 85, 256, 1000, pl, None) == _lib.FDAS_UNSUPPORTED
     assert na(sp, _fake(0x5000), 4, -1, bk, 85, 256, 2048, pl, None) == _lib.FDAS_INVALID_ARG
     assert _lib.NOALLOC_MAX_SPECTRA == 65536
+    # LDS bank probe: arguments checked before any launch
+    lp = L.fdas_lds_probe
+    assert lp(_fake(0x7000), 3, 16, 1, _fake(0x7100), _fake(0x7200), None) == _lib.FDAS_INVALID_ARG
+    assert lp(_fake(0x7000), 0, 0, 1, _fake(0x7100), _fake(0x7200), None) == _lib.FDAS_INVALID_ARG
+    assert lp(_fake(0x7000), 1, 16, 0, _fake(0x7100), _fake(0x7200), None) == _lib.FDAS_INVALID_ARG
+    assert lp(None, 1, 16, 1, _fake(0x7100), _fake(0x7200), None) == _lib.FDAS_INVALID_ARG
+    assert lp(_fake(0x7000), 1, 16, 1, _fake(0x7104), _fake(0x7200), None) == _lib.FDAS_INVALID_ARG
     # batched adjoint: workspace by the gradients wanted, validation first
     wb = L.fdas_backward_batched_workspace_bytes
     both, only_s, only_t = wb(cap, 4, 9, 128, 2048, 0, 3), wb(cap, 4, 9, 128, 2048, 0, 1), wb(cap, 4, 9, 128, 2048, 0, 2)

@@ -277,8 +277,12 @@ def test_emulated_backward_batched_empty_batch(emu):
 # window chunks
 # M = L/4 at 8 values per lane puts M/2 on exactly one lane slot at each end
 # (512/128, 1024/256, 2048/512): the kernels specialised for those edge slots
+# M/2 = T (512/128, 256/128) runs the windows in groups of three that share
+# one taps transform per template: 2, 7 and 8 windows leave groups of 2, 1
+# and 2 at the end
 @pytest.mark.parametrize("L,M,N", [(256, 32, 900), (512, 128, 600), (2048, 256, 2500),
-                                   (256, 32, 29131), (1024, 256, 1500), (2048, 512, 2600)])
+                                   (256, 32, 29131), (1024, 256, 1500), (2048, 512, 2600),
+                                   (512, 128, 2500), (256, 128, 1000)])
 def test_emulated_backward_vs_oracle(emu, L, M, N):
     K = 3
     A = syn.random_spectrum(3 * L, N)
