@@ -359,14 +359,14 @@ __device__ __forceinline__ void run_passes(const float2 (&in)[E], const float2 (
                 w[i] = tw[OFF + u * (R - 1) + (i - 1)];
             dft_mul<R, INV, INV ? kMulConj : kMul, true>(x, w);
         } else if constexpr (NS > 1) {
-            // twiddles W_L^((j mod NS) i L / (NS R)) from the LDS table
-            // (entries W_L^n, n < NS)
-            const int base = ((t + u * T) & (NS - 1)) * (L / (NS * R));
+            // twiddles W_{NS R}^(c i), c = j mod NS, from the LDS table laid
+            // out [i - 1][c] (the lanes of a row read consecutive entries)
+            const int c = (t + u * T) & (NS - 1);
             float2 w[R];
             w[0] = make_float2(1.f, 0.f);
 #pragma unroll
             for (int i = 1; i < R; ++i)
-                w[i] = twl[base * i];
+                w[i] = twl[(i - 1) * NS + c];
             dft_mul<R, INV, INV ? kMulConj : kMul, true>(x, w);
         } else if constexpr (MODE0 != kNoMul) {
             float2 w[R];
@@ -418,6 +418,16 @@ __device__ __forceinline__ void run_passes(const float2 (&in)[E], const float2 (
 template <int L, int E, class RL>
 struct FFT;
 
+// Radix of the pass whose stride is NS_AT (0 if none).
+template <int NS_AT, int NS, int... Rs>
+struct RadixAt {
+    static constexpr int value = 0;
+};
+template <int NS_AT, int NS, int R, int... Rest>
+struct RadixAt<NS_AT, NS, R, Rest...> {
+    static constexpr int value = NS == NS_AT ? R : RadixAt<NS_AT, NS * R, Rest...>::value;
+};
+
 template <int... Rs>
 struct LastRadix;
 template <int R>
@@ -432,11 +442,16 @@ struct LastRadix<R, R2, Rest...> {
 template <int L, int E, int... Rs>
 struct FFT<L, E, Radices<Rs...>> {
     static constexpr int T = L / E;
-    // At L = 8192 the last pass is radix 2 with stride NS = L/2; its
-    // twiddles W_L^n (n < L/2, one per butterfly) come from a 32 KB table in
-    // LDS, which frees the registers the longest transform runs short of.
+    // One pass may take its twiddles from a table in LDS instead of
+    // registers: at L = 8192 the last one (radix 2, stride L/2: one twiddle
+    // per butterfly, a 32 KB table), which frees the registers the longest
+    // transform runs short of.  (Taking the second pass's 15 twiddles per
+    // lane from LDS in the interbinned kernel freed 20 VGPRs there but timed
+    // 0.2 % slower.)
     static constexpr int kLNS = (L >= 8192 && LastRadix<Rs...>::value == 2) ? L / 2 : 0;
-    static constexpr int kLdsTw = kLNS;                 // table entries
+    static constexpr int kLR = kLNS > 0 ? RadixAt<kLNS, 1, Rs...>::value : 0;
+    static_assert(kLNS == 0 || kLR > 0, "the LDS-twiddle stride must be a pass's");
+    static constexpr int kLdsTw = kLNS > 0 ? (kLR - 1) * kLNS : 0;   // table entries
     static constexpr int kLdsTwAlloc = kLdsTw > 0 ? kLdsTw : 1;
     static constexpr int NTW = TwiddleCount<L, E, 1, kLNS, Radices<Rs...>>::value > 0
                                    ? TwiddleCount<L, E, 1, kLNS, Radices<Rs...>>::value : 1;
@@ -457,8 +472,11 @@ struct FFT<L, E, Radices<Rs...>> {
     {
         load_twiddles<L, E, 1, 0, NTW, kLNS, Rs...>(tw.r, table, t);
         if constexpr (kLdsTw > 0) {
-            for (int n = t; n < kLdsTw; n += T)
-                lds_table[n] = table[n];
+            // entry (i - 1) kLNS + c = W_{kLNS kLR}^(c i) = W_L^(c i L / (kLNS kLR))
+            for (int n = t; n < kLdsTw; n += T) {
+                const int i = n / kLNS + 1, c = n % kLNS;
+                lds_table[n] = table[c * i * (L / (kLNS * kLR))];
+            }
         }
         tw.lds = lds_table;
     }

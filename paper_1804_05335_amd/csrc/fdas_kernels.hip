@@ -193,7 +193,8 @@ struct Fwd {
                                 const float2* __restrict__ bank, int K, int M, int64_t s, int z0,
                                 int z1, float* __restrict__ plane, const typename F::TW& tw,
                                 float2*& la, float2*& lb, int t, float2 (&H)[E],
-                                const float2* __restrict__ bank2 = nullptr)
+                                const float2* __restrict__ bank2 = nullptr,
+                                float2* __restrict__ edge = nullptr)
     {
         const int B = L - M;
         const int64_t out0 = s * B;
@@ -259,19 +260,25 @@ struct Fwd {
                 // rotation within the wave (ds_bpermute, no LDS storage) for
                 // lanes 0..62; lane 63 takes the next wave's lane 0 at the same
                 // m, or in the last wave wave 0's lane 0 at m + 1, from a few
-                // LDS slots each wave's lane 0 fills ([NW][E + 1]; slot E is
-                // read only for position L, which is never a valid output).
+                // LDS slots each wave's lane 0 fills ([NW][E + 1], an array of
+                // their own below L = 8192, so the exchange buffers keep their
+                // parity across templates and their addresses stay
+                // loop-invariant; slot E is read only for position L, never a
+                // valid output).
                 // For valid outputs q + 1 <= M/2 + B = L - M/2 stays inside
                 // the segment.
                 constexpr int NW = T / 64;
                 const int lane = t & 63, wave = t >> 6;
-                float2* edge = la;
+                // at L = 8192 LDS is full: the slots borrow the free exchange
+                // buffer, which then swaps parity once more per template
+                constexpr bool OWN_EDGE = L < 8192;
+                float2* const ex = OWN_EDGE ? edge : la;
                 if (lane == 0) {
                     // slots DEAD .. E - DEAD: the live ones and, one past
                     // them, the spare output at L - M/2
 #pragma unroll
                     for (int m = DEAD; m < E - DEAD + (DEAD > 0 ? 1 : 0); ++m)
-                        edge[wave * (E + 1) + m] = v[m];
+                        ex[wave * (E + 1) + m] = v[m];
                 }
                 next();
                 __syncthreads();
@@ -287,7 +294,7 @@ struct Fwd {
                         __builtin_amdgcn_ds_bpermute(src, __float_as_int(v[m].x)));
                     float by = __int_as_float(
                         __builtin_amdgcn_ds_bpermute(src, __float_as_int(v[m].y)));
-                    const float2 e = edge[ew * (E + 1) + em + m];   // broadcast read
+                    const float2 e = ex[ew * (E + 1) + em + m];     // broadcast read
                     bx = lane == 63 ? e.x : bx;
                     by = lane == 63 ? e.y : by;
                     const float p = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
@@ -297,9 +304,11 @@ struct Fwd {
                     __builtin_amdgcn_raw_buffer_store_b64(ph, rs, seg_off<8>(t + T * m, M / 2), 0,
                                                           kNonTemporal);
                 }
-                float2* tmp = la;
-                la = lb;
-                lb = tmp;
+                if constexpr (!OWN_EDGE) {
+                    float2* tmp = la;
+                    la = lb;
+                    lb = tmp;
+                }
             }
         };
         if constexpr (SYM) {
@@ -340,6 +349,7 @@ __global__ __launch_bounds__(Fwd<L>::T, 2) void forward_kernel(
     using W = Fwd<L>;
     __shared__ __align__(16) float2 lds[2][LdsSize<L>::value];
     __shared__ float2 twl[W::F::kLdsTwAlloc];
+    __shared__ float2 edge[IB && L < 8192 ? (W::T / 64) * (W::E + 1) : 1];   // interbinning
     int64_t i, i1;
     item_range(nseg * K, i, i1);
     if (i >= i1)
@@ -358,7 +368,7 @@ __global__ __launch_bounds__(Fwd<L>::T, 2) void forward_kernel(
         const int zs = (int)(i - s * K);
         const int ze = (int)min<int64_t>(K, zs + (i1 - i));
         W::template item<IB, SYM, DUAL, DEAD>(spec, N, bank, K, M, s, zs, ze, plane, tw, la, lb,
-                                               t, H, bank2);
+                                               t, H, bank2, edge);
         i += ze - zs;
     }
 }
