@@ -138,17 +138,18 @@ def hbm_stream(fdas, torch, nbytes: int, steps: int):
             "read_GBps": round(nbytes / ms_r / 1e6, 1), "read_sum_checked": ok}
 
 
-def kernel_sources_hash() -> str:
-    """First 16 hex digits of the sha256 over every library source file (all
-    of csrc/, in name order), so a counter summary is tied to the sources of
-    whichever kernel it profiles."""
+def kernel_sources_hash(files=None) -> str:
+    """First 16 hex digits of the sha256 over library source files of csrc/
+    (the named ones, else all of them), in name order, so a counter summary
+    is tied to the sources of the kernel it profiles."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1804_05335_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
-            h.update(f.encode())
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+    names = sorted(files) if files else sorted(
+        f for f in os.listdir(csrc) if f.endswith((".hip", ".hpp", ".cpp", ".h")))
+    for f in names:
+        h.update(f.encode())
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -163,7 +164,8 @@ def read_summary(name: str):
         if ":" in line and not line.startswith(("#", "|", " ")):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_sources_hash") != kernel_sources_hash():
+    files = vals.get("kernel_sources", "").split() or None
+    if vals.get("kernel_sources_hash") != kernel_sources_hash(files):
         return None
     return vals
 
@@ -645,13 +647,17 @@ def bench_sym(fdas, torch, steps: int):
     return out
 
 
+R2C_SIZES = (22, 23, 24)
+
+
 def bench_r2c(fdas, torch, steps: int):
     """Real-to-complex front end on 2^22, 2^23 and 2^24 FP32 samples (the
-    paper's signal lengths): time per call with the series resident in HBM,
-    against the algorithmic bytes (read 4n, write 8(n/2 + 1))."""
+    paper's signal lengths; R2C_SIZES): time per call with the series resident
+    in HBM, against the algorithmic bytes (read 4n, write 8(n/2 + 1)); then a
+    batch of 64 series of 2^22 samples (unless R2C_SIZES was narrowed)."""
     import fdas_synth as syn
     out = {}
-    for log2n in (22, 23, 24):
+    for log2n in R2C_SIZES:
         n = 1 << log2n
         x = torch.from_numpy(syn.time_series(log2n, n)).cuda()
         spec = torch.empty(n // 2 + 1, dtype=torch.complex64, device="cuda")
@@ -670,6 +676,8 @@ def bench_r2c(fdas, torch, steps: int):
         del x, spec, ws
     torch.cuda.empty_cache()
     out["paper_cpu_r2c_ms"] = {"2^21": 30, "2^22": 75, "2^23": 220}
+    if tuple(R2C_SIZES) != (22, 23, 24):
+        return out
     # 64 series of 2^22 samples (equal-length dedispersion trials): one
     # launch per pass for the batch against a loop of single-series calls
     n, S = 1 << 22, 64
@@ -834,9 +842,14 @@ def main() -> int:
     ap.add_argument("--extras", default="batched,fwd_bwd,large_zmax,interbin,sym,r2c,harmonic,pipeline",
                     help="comma-separated extra comparisons to run")
     ap.add_argument("--extra-steps", type=int, default=5)
+    ap.add_argument("--r2c-sizes", default="22,23,24",
+                    help="log2 of the sample counts of the r2c leg (another list skips its "
+                         "batched part; for one-size counter summaries)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one plain device copy of BYTES (reference for HBM counters)")
     args = ap.parse_args()
+    global R2C_SIZES
+    R2C_SIZES = tuple(int(x) for x in args.r2c_sizes.split(",") if x)
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU only (got --gpus {args.gpus}); "
               "the forward path shards by spectrum or segment range with no exchange, "

@@ -74,9 +74,51 @@ def dispatches(rows, match):
     return out
 
 
+def trace(args, cmd) -> int:
+    """--trace: one rocprofv3 --kernel-trace --stats run; the summary lists the
+    calls and mean / min / max duration of every kernel matching --kernel
+    (a comma-separated list of name substrings)."""
+    from bench import kernel_sources_hash
+
+    outdir = args.workdir
+    os.makedirs(outdir, exist_ok=True)
+    full = ["timeout", "-s", "KILL", str(args.limit), "rocprofv3", "--kernel-trace", "--stats",
+            "-f", "csv", "-d", outdir, "-o", "t", "--", *cmd]
+    print("# " + " ".join(shlex.quote(c) for c in full), flush=True)
+    with open(os.path.join(outdir, "run.log"), "w") as log:
+        rc = subprocess.run(full, stdout=log, stderr=subprocess.STDOUT).returncode
+    files = glob.glob(os.path.join(outdir, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"rocprofv3 trace failed with status {rc} (see {outdir})")
+    rows = list(csv.DictReader(open(files[0])))
+    pats = [p for p in args.kernel.split(",") if p]
+    cmdline = "python3 profile_counters.py " + " ".join(shlex.quote(a) for a in sys.argv[1:])
+    lines = [f"# {args.title}", "", "Made by (from the repository root, TMPDIR=/tmp):", "",
+             f"    {cmdline}", "", "which runs:", "",
+             "    rocprofv3 --kernel-trace --stats -f csv -d <out> -o t -- " +
+             " ".join(shlex.quote(c) for c in cmd), "",
+             "| kernel | calls | mean us | min us | max us |", "|---|---|---|---|---|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        if pats and not any(p in r["Name"] for p in pats):
+            continue
+        lines.append(f"| `{r['Name'][:110]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} |")
+    if args.note:
+        lines += ["", args.note]
+    files_h = args.sources.split() or None
+    lines += ["", f"kernel_sources: {' '.join(sorted(files_h)) if files_h else ''}",
+              f"kernel_sources_hash: {kernel_sources_hash(files_h)}", ""]
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines))
+    print(f"# wrote {args.out}", flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--kernel", required=True, help="substring of the kernel's name")
+    ap.add_argument("--trace", action="store_true",
+                    help="a kernel trace with per-kernel duration statistics instead of counters")
     ap.add_argument("--out", required=True, help="summary file (Markdown)")
     ap.add_argument("--title", required=True)
     ap.add_argument("--note", default="", help="paragraph appended to the summary")
@@ -86,11 +128,20 @@ def main() -> int:
     ap.add_argument("--limit", type=int, default=150, help="seconds per pass")
     ap.add_argument("--algorithmic-bytes", type=float, default=0.0,
                     help="algorithmic HBM bytes per launch, for the comparison line")
+    ap.add_argument("--grid-size", type=int, default=0,
+                    help="only dispatches of this grid size (total lanes)")
+    ap.add_argument("--largest", action="store_true",
+                    help="only the dispatches of the largest grid size among the matches")
+    ap.add_argument("--sources", default="",
+                    help="the csrc/ files the kernel is built from (space-separated; "
+                         "default: all of csrc/), hashed into the summary")
     ap.add_argument("cmd", nargs=argparse.REMAINDER)
     args = ap.parse_args()
     cmd = args.cmd[1:] if args.cmd[:1] == ["--"] else args.cmd
     if not cmd:
         ap.error("no command after --")
+    if args.trace:
+        return trace(args, cmd)
     from bench import kernel_sources_hash
 
     values, names, shapes, calib, commands = {}, set(), set(), {}, []
@@ -99,6 +150,11 @@ def main() -> int:
         commands.append("rocprofv3 --pmc " + " ".join(counters) + " -f csv -d <out> -o p -- " +
                         " ".join(shlex.quote(c) for c in cmd))
         sel = dispatches(rows, args.kernel)
+        if args.grid_size:
+            sel = {k: v for k, v in sel.items() if v[1] == args.grid_size}
+        if args.largest and sel:
+            top = max(v[1] for v in sel.values())
+            sel = {k: v for k, v in sel.items() if v[1] == top}
         if not sel:
             raise SystemExit(f"no dispatch of a kernel matching {args.kernel!r} in pass {counters}")
         for name, grid, wg, lds, cv in sel.values():
@@ -125,13 +181,14 @@ def main() -> int:
     valu = mean.get("SQ_INSTS_VALU", 0.0)
     issue = valu * 4 / (cycles * SIMDS) if cycles else 0.0
 
+    cmdline = "python3 profile_counters.py " + " ".join(shlex.quote(a) for a in sys.argv[1:])
     lines = [f"# {args.title}", "",
              f"Kernel: `{name}`, mean over {ndisp} dispatches of one size.",
              f"Launch: grid {grid // wg} workgroups x {wg} lanes, LDS {lds} B per workgroup.",
-             "Library sources: `kernel_sources_hash` below (sha256 over "
-             "paper_1804_05335_amd/csrc/, first 16 hex).", "",
-             "Made by `python3 profile_counters.py` (run from the repository root with "
-             "TMPDIR=/tmp), one rocprofv3 run per counter pass:", ""]
+             "Sources: `kernel_sources_hash` below (sha256 over the csrc/ files named in "
+             "`kernel_sources`, or all of paper_1804_05335_amd/csrc/, first 16 hex).", "",
+             "Made by (from the repository root, TMPDIR=/tmp):", "", f"    {cmdline}", "",
+             "which makes one rocprofv3 run per counter pass:", ""]
     lines += [f"    {c}" for c in commands]
     lines += ["", f"## Calibration: plain device copy of {args.copy_bytes} B (`{COPY_KERNEL}`)", ""]
     if calib:
@@ -156,7 +213,9 @@ def main() -> int:
                  f"written = {(fetch + write) / 1e6:.1f} MB{alg}.")
     if args.note:
         lines += ["", args.note]
-    lines += ["", f"kernel_sources_hash: {kernel_sources_hash()}",
+    files = args.sources.split() or None
+    lines += ["", f"kernel_sources: {' '.join(sorted(files)) if files else ''}",
+              f"kernel_sources_hash: {kernel_sources_hash(files)}",
               f"fetch_bytes_per_launch: {fetch:.0f}",
               f"write_bytes_per_launch: {write:.0f}",
               f"valu_insts_per_launch: {valu:.0f}",

@@ -72,7 +72,7 @@ def test_traffic_only_from_summaries_of_the_current_sources(tmp_path, monkeypatc
     cur = bench.kernel_sources_hash()
     os.makedirs(tmp_path / "profiles")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    monkeypatch.setattr(bench, "kernel_sources_hash", lambda: cur)
+    monkeypatch.setattr(bench, "kernel_sources_hash", lambda files=None: cur)
     _summary(tmp_path / "profiles" / "now.md", cur, 100, 23)
     _summary(tmp_path / "profiles" / "old.md", "0" * 16, 100, 23)
     assert bench.read_traffic("now.md") == 123.0
@@ -83,3 +83,6 @@ def test_traffic_only_from_summaries_of_the_current_sources(tmp_path, monkeypatc
 def test_kernel_sources_hash_is_stable_and_short():
     a, b = bench.kernel_sources_hash(), bench.kernel_sources_hash()
     assert a == b and len(a) == 16 and int(a, 16) >= 0
+    # a summary can name the files of its kernel: the hash then covers those only
+    f = bench.kernel_sources_hash(["fdas_r2c.hip", "fdas_fft.hpp"])
+    assert f == bench.kernel_sources_hash(["fdas_fft.hpp", "fdas_r2c.hip"]) and f != a
