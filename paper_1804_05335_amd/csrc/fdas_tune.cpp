@@ -255,11 +255,11 @@ int fdas_autotune_batched(const fdas_cf32* taps_dev, int K, int M, const fdas_cf
     }
     std::vector<double> best_ms(ncand, 1e300);
     int status = FDAS_OK;
-    // two rounds over the candidates (the bank is prepared once per L and
+    // three rounds over the candidates (the bank is prepared once per L and
     // round), each candidate one warm-up launch and the mean of three; the
-    // better of its two rounds counts, so a clock change during one round
-    // does not decide the choice
-    for (int round = 0; round < 2 && status == FDAS_OK; ++round) {
+    // best of its rounds counts, so a clock change during one round does
+    // not decide the choice
+    for (int round = 0; round < 3 && status == FDAS_OK; ++round) {
         int bankL = 0;
         for (int c = 0; c < ncand && status == FDAS_OK; ++c) {
             const int L = cand[c].L, E = cand[c].E;

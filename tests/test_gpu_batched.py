@@ -168,7 +168,8 @@ def _tune_batch(fd, nspec, scale):
 def test_autotuner_within_3_percent_of_exhaustive_sweep(fd):
     # a small batch (32 spectra of ~2^15..2^18 bins); the tuner's choice
     # (timed afresh, caches bypassed) against an exhaustive sweep of the same
-    # candidates, each timed in three interleaved rounds (best round counts)
+    # candidates, each timed in five interleaved rounds of five launches (best
+    # round counts), after the device has been kept busy for a while
     w, K, M, taps, specs, offs, o, planes, ws = _tune_batch(fd, 32, 1 / 8)
     nspec = len(w.spectra)
     t = fd._lib.fdas_autotune_batched(taps, K, M, specs, offs, nspec, planes, ws,
@@ -180,7 +181,11 @@ def test_autotuner_within_3_percent_of_exhaustive_sweep(fd):
     bws = torch.empty(fd.fdas_batched_workspace_bytes(nspec), dtype=torch.uint8, device="cuda")
     best = {}
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    for _ in range(3):
+    for _ in range(6):
+        fd.fdas_correlate_batched_ex(specs, offs, nspec, banks[t["L"]], K, M, t["L"], planes, 0, 0,
+                                     bws)
+    torch.cuda.synchronize()
+    for _ in range(5):
         for c in cands:
             grid = 0 if c["grid_factor"] == 1 else \
                 c["grid_factor"] * fd._lib.fdas_batched_resident_grid(c["L"], c["E"], M)
@@ -190,12 +195,12 @@ def test_autotuner_within_3_percent_of_exhaustive_sweep(fd):
                                              planes, c["E"], grid, bws)
             run()
             ev[0].record()
-            for _ in range(3):
+            for _ in range(5):
                 run()
             ev[1].record()
             torch.cuda.synchronize()
             key = (c["L"], c["E"], c["grid_factor"])
-            best[key] = min(best.get(key, 1e30), ev[0].elapsed_time(ev[1]) / 3)
+            best[key] = min(best.get(key, 1e30), ev[0].elapsed_time(ev[1]) / 5)
     fastest = min(best.values())
     chosen = best[(t["L"], t["E"], t["grid_factor"])]
     assert chosen <= 1.03 * fastest, (t, chosen, fastest, best)
