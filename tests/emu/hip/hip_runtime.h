@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <memory>
 #include <thread>
 #include <vector>
 
@@ -93,6 +94,13 @@ inline thread_local EmuIdx threadIdx;
 inline EmuIdx blockIdx, gridDim, blockDim;
 inline std::barrier<>* emu_barrier = nullptr;
 inline void __syncthreads() { emu_barrier->arrive_and_wait(); }
+// A wave's lanes run as separate threads here, so a wave-local exchange
+// through LDS needs a barrier over the wave's 64 threads (on the GPU a wave's
+// LDS accesses are in order and the builtin only fences the compiler).
+inline std::vector<std::barrier<>*> emu_wave_barriers;
+inline void emu_wave_barrier() { emu_wave_barriers[threadIdx.x / 64]->arrive_and_wait(); }
+#define __builtin_amdgcn_wave_barrier emu_wave_barrier
+#define __builtin_amdgcn_fence(order, scope) std::atomic_thread_fence(std::memory_order_seq_cst)
 
 using std::max;
 using std::min;
@@ -153,6 +161,12 @@ void emu_launch(K kernel, dim3 grid, dim3 block, A... args)
                 blockIdx = EmuIdx{bx, by, bz};
                 std::barrier<> bar(block.x);
                 emu_barrier = &bar;
+                std::vector<std::unique_ptr<std::barrier<>>> wbars;
+                emu_wave_barriers.clear();
+                for (unsigned w0 = 0; w0 < block.x; w0 += 64) {
+                    wbars.emplace_back(new std::barrier<>(std::min(64u, block.x - w0)));
+                    emu_wave_barriers.push_back(wbars.back().get());
+                }
                 std::vector<std::thread> th;
                 th.reserve(block.x);
                 for (unsigned t = 0; t < block.x; ++t)
