@@ -99,6 +99,13 @@ hipError_t launch_prepare_bank(const float2* taps, int K, int M, int L, float2* 
 }
 
 // ---- fused forward correlation ---------------------------------------------
+
+// DPP lane patterns (gfx9 wave-wide forms): lane i reads lane i + 1
+// (lane 63 reads nothing), or lane (i + 1) mod 64.
+constexpr int kDppWaveShl1 = 0x130;
+constexpr int kDppWaveRol1 = 0x134;
+constexpr float kQuarterPi2 = 0.61685027506808491368f;   // (pi/4)^2, interbinning
+
 //
 // Segment s produces the B = L - M outputs [s B, s B + B) from the window of
 // input bins [s B - M/2, s B - M/2 + L) (zero outside [0, N)):
@@ -116,6 +123,12 @@ struct Fwd {
     using F = FFT<L, E, typename Plan<L, E>::R>;
     static constexpr int T = F::T;
     static constexpr int NTW = F::NTW;
+    // interbinned epilogue: waves per workgroup, and the `edge` slots
+    // ([wave][E + 1]) of several waves below L = 8192 (at 8192 LDS is full:
+    // the slots borrow the free exchange buffer)
+    static constexpr int IB_NW = T / 64;
+    static constexpr bool IB_OWN_EDGE = IB_NW > 1 && L < 8192;
+    static constexpr int kEdgeAlloc = IB_OWN_EDGE ? IB_NW * (E + 1) : 1;
 
     __device__ static void load_row(float2 (&H)[E], const float2* __restrict__ bank, int row,
                                     int t)
@@ -176,7 +189,7 @@ struct Fwd {
     //
     // IB (interbinning, Sec. 3 eq. f-interp): the plane has 2N columns per
     // row; column 2r holds |y_r|^2 and column 2r+1 |(pi/4)(y_r - y_{r+1})|^2.
-    // Each lane gets its right-hand neighbour's y by a lane rotation; the
+    // Each lane gets its right-hand neighbour's y by a DPP lane shift; the
     // segment's spare valid output supplies y_{r+1} for its last output.
     //
     // DUAL (two-bin Fourier interpolation): bank2 holds the half-bin
@@ -255,24 +268,51 @@ struct Fwd {
                                                           seg_off<4>(t + T * m, M / 2), 0,
                                                           kNonTemporal);
                 }
+            } else if constexpr (IB_NW == 1) {
+                // one wave: y at q + 1 = (t + 1) + 64 m is lane t + 1's
+                // v[m], and for lane 63 lane 0's v[m + 1]; lane 0 offers
+                // v[m + 1] instead of v[m] and a rotation by one lane hands
+                // every lane its neighbour (slot E, position L, is never a
+                // valid output)
+                next();
+                const int lane = t & 63;
+                const float* row_q0 = plane + 2 * ((int64_t)z * N + out0 - M / 2);
+                const auto rs = seg_rsrc(row_q0, (M / 2 + nvalid) * 8);
+#pragma unroll
+                for (int m = DEAD; m < E - DEAD; ++m) {
+                    const float2 nx = m + 1 < E ? v[m + 1] : v[m];
+                    const float sx = lane == 0 ? nx.x : v[m].x;
+                    const float sy = lane == 0 ? nx.y : v[m].y;
+                    const float dx = __int_as_float(__builtin_amdgcn_mov_dpp(
+                                         __float_as_int(sx), kDppWaveRol1, 0xf, 0xf, true)) -
+                                     v[m].x;
+                    const float dy = __int_as_float(__builtin_amdgcn_mov_dpp(
+                                         __float_as_int(sy), kDppWaveRol1, 0xf, 0xf, true)) -
+                                     v[m].y;
+                    const float p = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
+                    const float h = kQuarterPi2 * fmaf(dx, dx, dy * dy);
+                    const u32x2 ph = {__float_as_uint(p), __float_as_uint(h)};
+                    __builtin_amdgcn_raw_buffer_store_b64(ph, rs, seg_off<8>(t + T * m, M / 2), 0,
+                                                          kNonTemporal);
+                }
             } else {
-                // y at q + 1 = (t + 1) + T m is lane t + 1's v[m]: a lane
-                // rotation within the wave (ds_bpermute, no LDS storage) for
-                // lanes 0..62; lane 63 takes the next wave's lane 0 at the same
-                // m, or in the last wave wave 0's lane 0 at m + 1, from a few
-                // LDS slots each wave's lane 0 fills ([NW][E + 1], an array of
-                // their own below L = 8192, so the exchange buffers keep their
-                // parity across templates and their addresses stay
-                // loop-invariant; slot E is read only for position L, never a
-                // valid output).
-                // For valid outputs q + 1 <= M/2 + B = L - M/2 stays inside
-                // the segment.
-                constexpr int NW = T / 64;
+                // several waves: lanes 0..62 take lane t + 1's v[m] by a lane
+                // shift; lane 63 takes the next wave's lane 0 at the same m,
+                // or in the last wave wave 0's lane 0 at m + 1, from slots
+                // each wave's lane 0 fills behind a barrier of their own (an
+                // array of their own below L = 8192, so the exchange buffers
+                // keep their parity across templates and their addresses stay
+                // loop-invariant; at 8192 the free exchange buffer, which
+                // then swaps parity once more per template; slot E is read
+                // only for position L, never a valid output).  For valid
+                // outputs q + 1 <= M/2 + B = L - M/2 stays inside the
+                // segment.  Deferring lane 63's pairs to the next transform's
+                // first barrier instead leaves 8-byte holes in the plane's
+                // lines that a second, partial write fills: measured 1.4-1.8x
+                // slower.
+                constexpr int NW = IB_NW;
                 const int lane = t & 63, wave = t >> 6;
-                // at L = 8192 LDS is full: the slots borrow the free exchange
-                // buffer, which then swaps parity once more per template
-                constexpr bool OWN_EDGE = L < 8192;
-                float2* const ex = OWN_EDGE ? edge : la;
+                float2* const ex = IB_OWN_EDGE ? edge : la;
                 if (lane == 0) {
                     // slots DEAD .. E - DEAD: the live ones and, one past
                     // them, the spare output at L - M/2
@@ -282,29 +322,26 @@ struct Fwd {
                 }
                 next();
                 __syncthreads();
-                const int src = ((lane + 1) & 63) << 2;
                 const int ew = wave + 1 < NW ? wave + 1 : 0;
                 const int em = wave + 1 < NW ? 0 : 1;
-                constexpr float kQ2 = 0.61685027506808491368f;   // (pi/4)^2
                 const float* row_q0 = plane + 2 * ((int64_t)z * N + out0 - M / 2);
                 const auto rs = seg_rsrc(row_q0, (M / 2 + nvalid) * 8);
 #pragma unroll
                 for (int m = DEAD; m < E - DEAD; ++m) {
-                    float bx = __int_as_float(
-                        __builtin_amdgcn_ds_bpermute(src, __float_as_int(v[m].x)));
-                    float by = __int_as_float(
-                        __builtin_amdgcn_ds_bpermute(src, __float_as_int(v[m].y)));
                     const float2 e = ex[ew * (E + 1) + em + m];     // broadcast read
-                    bx = lane == 63 ? e.x : bx;
-                    by = lane == 63 ? e.y : by;
+                    // lane t + 1's v[m]; lane 63 keeps e
+                    const float bx = __int_as_float(__builtin_amdgcn_update_dpp(
+                        __float_as_int(e.x), __float_as_int(v[m].x), kDppWaveShl1, 0xf, 0xf, false));
+                    const float by = __int_as_float(__builtin_amdgcn_update_dpp(
+                        __float_as_int(e.y), __float_as_int(v[m].y), kDppWaveShl1, 0xf, 0xf, false));
                     const float p = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
                     const float dx = v[m].x - bx, dy = v[m].y - by;
-                    const float h = kQ2 * fmaf(dx, dx, dy * dy);
+                    const float h = kQuarterPi2 * fmaf(dx, dx, dy * dy);
                     const u32x2 ph = {__float_as_uint(p), __float_as_uint(h)};
                     __builtin_amdgcn_raw_buffer_store_b64(ph, rs, seg_off<8>(t + T * m, M / 2), 0,
                                                           kNonTemporal);
                 }
-                if constexpr (!OWN_EDGE) {
+                if constexpr (!IB_OWN_EDGE) {
                     float2* tmp = la;
                     la = lb;
                     lb = tmp;
@@ -349,7 +386,7 @@ __global__ __launch_bounds__(Fwd<L>::T, 2) void forward_kernel(
     using W = Fwd<L>;
     __shared__ __align__(16) float2 lds[2][LdsSize<L>::value];
     __shared__ float2 twl[W::F::kLdsTwAlloc];
-    __shared__ float2 edge[IB && L < 8192 ? (W::T / 64) * (W::E + 1) : 1];   // interbinning
+    __shared__ __align__(16) float2 edge[IB ? W::kEdgeAlloc : 1];   // interbinning
     int64_t i, i1;
     item_range(nseg * K, i, i1);
     if (i >= i1)

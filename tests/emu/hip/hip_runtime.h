@@ -120,6 +120,33 @@ inline int emu_ds_bpermute(int addr, int data)
     __syncthreads();
     return v;
 }
+// DPP moves, for the two wave-wide patterns the kernels use: 0x130 (lane i
+// reads lane i + 1; lane 63 has no source) and 0x134 (lane i reads lane
+// (i + 1) mod 64).  A lane without a source gets 0 (bound_ctrl) or `old`.
+// Exchanged through a per-wave buffer between two wave barriers, so every
+// lane of the wave must reach it (uniform control flow, as in the kernels).
+inline int emu_dpp_buf[1024];
+inline int emu_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl)
+{
+    if ((ctrl != 0x130 && ctrl != 0x134) || row_mask != 0xf || bank_mask != 0xf)
+        std::abort();
+    const unsigned t = threadIdx.x, lane = t & 63u, base = t & ~63u;
+    emu_dpp_buf[t] = src;
+    emu_wave_barrier();
+    int v;
+    if (ctrl == 0x134 || lane < 63)
+        v = emu_dpp_buf[base + ((lane + 1) & 63u)];
+    else
+        v = bound_ctrl ? 0 : old;
+    emu_wave_barrier();
+    return v;
+}
+inline int emu_mov_dpp(int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl)
+{
+    return emu_update_dpp(0, src, ctrl, row_mask, bank_mask, bound_ctrl);
+}
+#define __builtin_amdgcn_update_dpp emu_update_dpp
+#define __builtin_amdgcn_mov_dpp emu_mov_dpp
 inline long long clock64() { return 0; }
 inline unsigned atomicAdd(unsigned* p, unsigned v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
 inline void sincospi(double x, double* s, double* c) { *s = std::sin(M_PI * x); *c = std::cos(M_PI * x); }

@@ -278,11 +278,11 @@ def test_emulated_backward_batched_empty_batch(emu):
 # M = L/4 at 8 values per lane puts M/2 on exactly one lane slot at each end
 # (512/128, 1024/256, 2048/512): the kernels specialised for those edge slots
 # M/2 = T (512/128, 256/128) runs the windows in groups of three that share
-# one taps transform per template: 2, 7 and 8 windows leave groups of 2, 1
-# and 2 at the end
+# one taps transform per template: 2, 7, 5 and 8 windows leave groups of 2,
+# 1, 2 and 2 at the end
 @pytest.mark.parametrize("L,M,N", [(256, 32, 900), (512, 128, 600), (2048, 256, 2500),
                                    (256, 32, 29131), (1024, 256, 1500), (2048, 512, 2600),
-                                   (512, 128, 2500), (256, 128, 1000)])
+                                   (512, 128, 2500), (512, 128, 1700), (256, 128, 1000)])
 def test_emulated_backward_vs_oracle(emu, L, M, N):
     K = 3
     A = syn.random_spectrum(3 * L, N)
@@ -310,8 +310,13 @@ def test_emulated_backward_vs_oracle(emu, L, M, N):
 
 # 2048/256 and 2048/512 leave one and two lane slots at each end without
 # valid outputs (the kernels skip them at compile time)
+# lane 63's neighbour: a lane rotation in one wave (L <= 1024), LDS slots
+# behind a barrier with several waves (2048, 4096; over many templates,
+# segments and workgroup ranges)
 @pytest.mark.parametrize("L,M,N,grid", [(256, 32, 1000, 0), (512, 64, 449, 3), (2048, 256, 1793, 0),
-                                        (256, 2, 37, 0), (2048, 512, 3100, 2)])
+                                        (256, 2, 37, 0), (2048, 512, 3100, 2),
+                                        (1024, 128, 2000, 2), (2048, 128, 4000, 3),
+                                        (4096, 256, 5000, 2)])
 def test_emulated_interbin_vs_oracle(emu, L, M, N, grid):
     from oracle import direct
     K = 3
