@@ -311,6 +311,19 @@ def _timed(torch, fn, steps):
     return a.elapsed_time(b) / steps
 
 
+def _rounds(torch, fns, steps, rounds=5, warm_s=0.2):
+    """Fastest mean ms per call of each fn over interleaved rounds, after
+    `warm_s` seconds of untimed calls (the clock ramps up after host work
+    and drifts over a run; the functions compared see the same state)."""
+    t_end = time.perf_counter() + warm_s
+    while time.perf_counter() < t_end:
+        for f in fns:
+            f()
+        torch.cuda.synchronize()
+    per = [[_timed(torch, f, steps) for f in fns] for _ in range(rounds)]
+    return [min(r[j] for r in per) for j in range(len(fns))]
+
+
 def autotune(fdas, torch, taps, K, M, specs, offs, nspec, planes):
     """Launch shape (L, E, grid) the library's autotuner picks for this batch
     (timed afresh: the on-disk cache is bypassed so the record reflects this
@@ -476,9 +489,8 @@ def bench_fwd_bwd(fdas, torch, steps: int):
         def bwd_spec_only():
             fdas.fdas_correlate_backward(spec, N, bank, K, M, L, wt, gs, None, ws)
 
-        fwd(); bwd(); bwd_spec_only()
-        per_L[L] = {"forward_ms": _timed(torch, fwd, steps), "backward_ms": _timed(torch, bwd, steps),
-                    "backward_spec_only_ms": _timed(torch, bwd_spec_only, steps)}
+        ms = _rounds(torch, (fwd, bwd, bwd_spec_only), steps)
+        per_L[L] = {"forward_ms": ms[0], "backward_ms": ms[1], "backward_spec_only_ms": ms[2]}
         del bank, ws
     L = min(per_L, key=lambda k: per_L[k]["forward_ms"] + per_L[k]["backward_ms"])
     ms_f, ms_b = per_L[L]["forward_ms"], per_L[L]["backward_ms"]
@@ -594,12 +606,7 @@ def bench_interbin(fdas, torch, steps: int):
     def fourier2():
         fdas.fdas_correlate_fourier2(spec, N, bank, bank_h, K, M, L, plane2)
 
-    for f in (plain, ib, fourier2):
-        for _ in range(5):
-            f()
-    ms_p = _timed(torch, plain, max(steps, 10))
-    ms_i = _timed(torch, ib, max(steps, 10))
-    ms_f = _timed(torch, fourier2, max(steps, 10))
+    ms_p, ms_i, ms_f = _rounds(torch, (plain, ib, fourier2), max(steps, 10))
     bytes_i = 8 * N + 8 * K * N + 8 * K * L
     out = {"workload": f"2^21 bins, {K} templates x {M} taps, segment {L}",
            "plain_ms": ms_p, "interbinned_ms": ms_i, "interbinned_over_plain": ms_i / ms_p,
@@ -633,11 +640,7 @@ def bench_sym(fdas, torch, steps: int):
         def half():
             fdas.fdas_correlate_sym(spec, N, sym, K, M, L, plane)
 
-        for f in (full, half):
-            for _ in range(3):
-                f()
-        ms_f = _timed(torch, full, max(steps, 5))
-        ms_s = _timed(torch, half, max(steps, 5))
+        ms_f, ms_s = _rounds(torch, (full, half), max(steps, 5))
         out[str(L)] = {"full_bank_ms": ms_f, "symmetric_bank_ms": ms_s,
                        "full_bank_MB": bank.numel() * 8 / 1e6, "symmetric_bank_MB": sym.numel() * 8 / 1e6,
                        "points_per_s_symmetric": K * N / ms_s * 1e3}
@@ -666,9 +669,7 @@ def bench_r2c(fdas, torch, steps: int):
         def call():
             fdas.fdas_r2c(x, n, 1.0, spec, ws)
 
-        for _ in range(3):
-            call()
-        ms = _timed(torch, call, max(steps, 10))
+        ms = _rounds(torch, (call,), max(steps, 10))[0]
         alg = 4 * n + 8 * (n // 2 + 1)
         out[f"2^{log2n}"] = {"ms": ms, "samples_per_s": n / ms * 1e3,
                              "algorithmic_GB_per_s": alg / ms / 1e6,
@@ -800,13 +801,13 @@ def bench_harmonic(fdas, torch, steps: int):
     for i, H in enumerate(folds):
         def one(i=i, H=H):
             fdas.fdas_harmonic_sum(plane, N, K, H, outs[i - 1] if i else None, outs[i])
-        ms = _timed(torch, one, max(steps, 10))
+        ms = _rounds(torch, (one,), max(steps, 10))[0]
         pts = outs[i].numel()
         alg = pts * 4 * ((H - H // 2 if i else H) + (1 if i else 0) + 1)
         out["folds"][str(H)] = {"ms": ms, "points": pts, "algorithmic_GB_per_s": alg / ms / 1e6}
         total_ms += ms
         total_bytes += alg
-    out["all_folds_ms"] = _timed(torch, all_folds, max(steps, 10))
+    out["all_folds_ms"] = _rounds(torch, (all_folds,), max(steps, 10))[0]
     out["all_folds_algorithmic_GB_per_s"] = total_bytes / out["all_folds_ms"] / 1e6
     S = outs[-1]
     thr = float(torch.quantile(S.reshape(-1)[: 1 << 24].float(), 1 - 3e-5).item())
