@@ -80,3 +80,25 @@ def test_interbin_workload2_sampled(fd):
     got = P2[torch.from_numpy(zi.astype(np.int64)).cuda(), torch.from_numpy(ci).cuda()].cpu().numpy()
     ref = native.interbin_points(w.spectra[0], ot.templates(w.zmax, w.dz, M), zi, ci)
     assert _rel(got, ref) < TOL
+
+
+# Lane 63's neighbour at the wave edges: a lane rotation in one-wave
+# workgroups (L = 1024), LDS slots behind a barrier with 2, 4 and 8 waves;
+# M/2 = 0, 1 and 2 lane slots without valid outputs at each end (the
+# kernels drop those slots at compile time).  Three segments and a ragged
+# tail; two persistent workgroups (many segments and templates each) and the
+# resident grid.
+@pytest.mark.parametrize("L,M", [(1024, 128), (1024, 256), (2048, 128), (2048, 512),
+                                 (4096, 256), (4096, 512), (4096, 1024), (8192, 512)])
+@pytest.mark.parametrize("grid", [2, 0])
+def test_interbin_wave_edges_random_taps(fd, L, M, grid):
+    K = 3
+    N = 3 * (L - M) + 37
+    taps = syn.random_taps(L + M, K, M)
+    bank = fd.prepare_bank(torch.from_numpy(taps).cuda(), L)
+    A = syn.random_spectrum(L + 3 * M, N)
+    spec = torch.from_numpy(A).cuda()
+    P2 = fd.correlate_interbin(spec, bank, K, M, L, grid=grid).cpu().numpy()
+    assert _rel(P2, direct.interbinned_power(A, taps)) < TOL
+    plain = fd.correlate(spec, bank, K, M, L).cpu().numpy()
+    assert np.array_equal(P2[:, 0::2], plain)
