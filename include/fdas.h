@@ -425,7 +425,7 @@ int fdas_batched_resident_grid(int L, int E, int M, int *grid);
  * launch shape per card by hand, Sec. 5.1.2): prepares a bank from taps_dev
  * for every candidate L (fdas_autotune_candidates) and times
  * fdas_correlate_batched_ex on the caller's batch for every candidate
- * (L, E, grid) in two rounds (per round one warm-up launch and the mean of
+ * (L, E, grid) in three rounds (per round one warm-up launch and the mean of
  * three; a candidate's better round counts), and writes the fastest to *out.
  * The choice is cached for the life of the process and in a JSON file
  * ($FDAS_TUNE_CACHE, an empty value disabling it; else
