@@ -146,6 +146,40 @@ def test_emulated_batched_equals_plain(emu):
             assert _rel(view, native.power(specs[b], taps)) < TOL
 
 
+def test_emulated_batched_noalloc_equals_workspace_call(emu):
+    # the allocation-free entry point (its segment prefix in the library's
+    # device array) against the workspace form, twice in a row, the second
+    # batch smaller: no state carries over between calls
+    L, M, K = 512, 64, 3
+    taps = syn.random_taps(11, K, M)
+    bank = _bank(emu, taps, L)
+    emu.fdas_batched_workspace_bytes.restype = ctypes.c_size_t
+    for call, lens in enumerate(([700, 0, 1, 448, 1203, 5], [97, 449])):
+        specs = [syn.random_spectrum(30 + 10 * call + i, n) for i, n in enumerate(lens)]
+        packed = np.concatenate(specs).astype(np.complex64)
+        offs = np.zeros(len(lens) + 1, dtype=np.int64)
+        offs[1:] = np.cumsum(lens)
+        tot = int(offs[-1])
+        wsb = emu.fdas_batched_workspace_bytes(len(lens))
+        ws = np.zeros(wsb, dtype=np.uint8)
+        ref = np.zeros(K * tot, dtype=np.float32)
+        assert emu.fdas_correlate_batched_ex(_p(packed), _p(offs), len(lens), ctypes.c_int64(tot),
+                                             _p(bank), K, M, L, _p(ref), 0, 0, _p(ws),
+                                             ctypes.c_size_t(wsb), None) == 0
+        buf, got = _guarded((K * tot,))
+        assert emu.fdas_correlate_batched_noalloc(_p(packed), _p(offs), len(lens),
+                                                  ctypes.c_int64(tot), _p(bank), K, M, L,
+                                                  _p(got), None) == 0
+        _check_guards(buf, got)
+        assert np.array_equal(got, ref), call
+    # past the fixed array: rejected before any launch
+    big = 65537
+    offs = np.zeros(big + 1, dtype=np.int64)
+    planes = np.zeros(1, dtype=np.float32)
+    spec = np.zeros(1, dtype=np.complex64)
+    assert emu.fdas_correlate_batched_noalloc(_p(spec), _p(offs), big, ctypes.c_int64(0),
+                                              _p(bank), K, M, L, _p(planes), None) != 0
+
 @pytest.mark.parametrize("L,E", [(1024, 8), (2048, 8), (1024, 16), (8192, 8), (4096, 8)])
 def test_emulated_batched_values_per_lane(emu, L, E):
     # the other lane geometry of the batched kernel: same plane up to FP32
