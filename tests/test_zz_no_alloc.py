@@ -6,7 +6,8 @@ twice in a row -- a larger batch, then a smaller one, so the second call
 runs over the first call's leftovers in that array -- its planes must equal
 (bitwise) those of fdas_correlate_batched with a workspace on the same
 inputs, and every output must be written.  Sizes beyond the array's maximum
-are rejected before anything is launched.
+are rejected before anything is launched.  Captured in a graph, for the
+callers it is for, it replays on new batches written in place.
 """
 import numpy as np
 import pytest
@@ -82,3 +83,53 @@ def test_noalloc_rejects_oversized_batch(fd):
     planes = torch.zeros(4 * K, dtype=torch.float32, device="cuda")
     with pytest.raises(fd.FdasError, match="allocation-free"):
         fd._lib.fdas_correlate_batched_noalloc(specs, offs, n, bank, K, M, L, planes)
+
+
+def test_noalloc_graph_replay_on_new_batches(fd):
+    # captured once; offsets and spectra rewritten in place before each
+    # replay, every replay equal to an eager call with a workspace, eager
+    # work in between
+    L, M, zmax = 512, 64, 20.0
+    taps, bank = fd.make_bank(zmax, 2.0, M, L)
+    K = taps.shape[0]
+    nspec, cap = 8, 120000
+    specs = torch.zeros(cap, dtype=torch.complex64, device="cuda")
+    offs = torch.zeros(nspec + 1, dtype=torch.int64, device="cuda")
+    planes = torch.zeros(K * cap, dtype=torch.float32, device="cuda")
+
+    def fill(seed):
+        rng = np.random.default_rng(seed)
+        lens = rng.integers(0, 15000, nspec)
+        o = np.zeros(nspec + 1, dtype=np.int64)
+        o[1:] = np.cumsum(lens)
+        specs[:o[-1]].copy_(torch.from_numpy(syn.random_spectrum(seed, int(o[-1]))))
+        offs.copy_(torch.from_numpy(o))
+        return o
+
+    def call():
+        fd._lib.fdas_correlate_batched_noalloc(specs, offs, nspec, bank, K, M, L, planes)
+
+    fill(1)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):   # warm-up outside capture
+        call()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        call()
+    ws = torch.empty(fd.fdas_batched_workspace_bytes(nspec), dtype=torch.uint8, device="cuda")
+    for seed in (2, 3, 4):
+        o = fill(seed)
+        planes.fill_(-1.0)
+        print(f"noalloc graph replay seed {seed}: bins={int(o[-1])}", flush=True)
+        g.replay()
+        torch.cuda.synchronize()
+        got = planes[:K * o[-1]].clone()
+        ref = torch.full((K * int(o[-1]),), float("nan"), dtype=torch.float32, device="cuda")
+        fd.fdas_correlate_batched(specs[:o[-1]], offs, nspec, bank, K, M, L, ref, ws)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), seed
+        _ = torch.randn(1000, device="cuda").sum()   # unrelated eager work between replays
